@@ -1,0 +1,92 @@
+"""Right-hand side of the global system (oracle, FP64).
+
+Sec. 2: f is replaced by its L2(Q) projection Q_h^0 f onto functions that
+are constant on every prism omega_j x (t_{l-1}, t_l); the coefficient f_{j,l}
+is the mean of f over that prism.  The load is then
+    F~ = M10 F C_t^T  in R^{M_x x N_t},   F[j, l] = f_{j,l},
+with M10 the M_{h_x}^{1,0} matrix and C_t the time matrix of H_T.
+
+Space means use a collapsed (Duffy) tensor Gauss rule on each triangle,
+exact for polynomials of total degree 2n-2 (n = points per direction);
+time means are exact antiderivatives.
+
+Parity status: pinned by tests (rule exactness on monomials, doubling of
+the rule, the exact mean of a linear function).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def triangle_rule(n: int):
+    """Nodes (bary coords l1, l2 with l0 = 1-l1-l2) and weights (sum 1) of the
+    collapsed Gauss rule on the reference triangle, n x n points."""
+    x, w = np.polynomial.legendre.leggauss(n)
+    x = 0.5 * (x + 1)
+    w = 0.5 * w
+    U, V = np.meshgrid(x, x, indexing="ij")
+    WU, WV = np.meshgrid(w, w, indexing="ij")
+    # (u, v) in [0,1]^2 -> (u, u v) in {0 <= y <= x <= 1}, Jacobian u; that
+    # triangle has area 1/2, so weights are normalised to sum to one
+    l1 = (U * (1 - V)).ravel()      # weight of vertex 1
+    l2 = (U * V).ravel()            # weight of vertex 2
+    wt = (2 * WU * WV * U).ravel()
+    return l1, l2, wt
+
+
+def space_means(mesh, fx, n: int = 8):
+    """Mean over every triangle of fx(x1, x2) (vectorised callable).
+
+    Returns (ntri,) array."""
+    xy = np.asarray(mesh.xy, dtype=np.float64)
+    tri = np.asarray(mesh.tri, dtype=np.int64)
+    l1, l2, wt = triangle_rule(n)
+    p0 = xy[tri[:, 0]][:, None, :]
+    p1 = xy[tri[:, 1]][:, None, :]
+    p2 = xy[tri[:, 2]][:, None, :]
+    P = p0 + l1[None, :, None] * (p1 - p0) + l2[None, :, None] * (p2 - p0)
+    vals = fx(P[..., 0], P[..., 1])
+    return (vals * wt[None, :]).sum(axis=1)
+
+
+def modes_cell_means(mesh, t, modes, n: int = 8):
+    """F[j, l] = mean of f over omega_j x (t_{l-1}, t_l) for
+    f = sum_q c_q sin(a_q pi xi1) sin(b_q pi xi2) cos(d_q pi t / T),
+    xi the bounding-box map of x onto [0,1]^2."""
+    t = np.asarray(t, dtype=np.float64)
+    T = t[-1]
+    h = np.diff(t)
+    xmin, xmax, ymin, ymax = mesh.box
+    F = np.zeros((len(mesh.tri), len(h)))
+    for a, b, d, c in zip(modes.a, modes.b, modes.d, modes.c):
+        def fx(x1, x2, a=a, b=b):
+            xi1 = (x1 - xmin) / (xmax - xmin)
+            xi2 = (x2 - ymin) / (ymax - ymin)
+            return np.sin(a * math.pi * xi1) * np.sin(b * math.pi * xi2)
+        sx = space_means(mesh, fx, n)
+        if d == 0:
+            st = np.ones_like(h)
+        else:
+            w = d * math.pi / T
+            st = (np.sin(w * t[1:]) - np.sin(w * t[:-1])) / (w * h)
+        F += c * np.outer(sx, st)
+    return F
+
+
+def manufactured_cell_means(mesh, t, n: int = 8):
+    """Cell means of f = (2t + 2 pi^2 t^2) sin(pi x1) sin(pi x2), the load of
+    u = sin(pi x1) sin(pi x2) t^2 (du/dt - Laplace u = f)."""
+    t = np.asarray(t, dtype=np.float64)
+    h = np.diff(t)
+    sx = space_means(mesh, lambda x1, x2: np.sin(math.pi * x1) * np.sin(math.pi * x2), n)
+    # int (2t + 2 pi^2 t^2) dt = t^2 + 2 pi^2 t^3 / 3
+    G = lambda s: s ** 2 + 2 * math.pi ** 2 * s ** 3 / 3
+    st = (G(t[1:]) - G(t[:-1])) / h
+    return np.outer(sx, st)
+
+
+def assemble_load(M10, F, Ct):
+    """F~ = M10 F C_t^T  (M_x x N_t)."""
+    return np.asarray(M10 @ F) @ np.asarray(Ct).T
