@@ -1,0 +1,231 @@
+/*
+ * stfd: space-time Fast Diagonalization solver for the heat equation on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Solves the space-time Galerkin system of Langer & Zank (arXiv 2008.01996)
+ *
+ *     K_h u = F~,   K_h = A_t (x) M_x + M_t (x) A_x            (Sec. 2)
+ *
+ * with P1 elements in 2D space, piecewise-linear time elements and the
+ * modified Hilbert transformation H_T, by the Fast Diagonalization method
+ * (Sec. 4.4, Algorithm FD):
+ *   1a  generalised eigendecomposition  M_t X = A_t X diag(lambda)
+ *   1b  singular value decomposition    X = U_t Sigma V_t^*
+ *   2   forward transform  G = F^ A_t^-1 conj(U_t) Sigma^-1 V_t^T
+ *   3   independent spatial solves  (M_x + lambda_k A_x) z_k = g_k
+ *   4   back transform  u = vec(Z X^T)
+ * followed by FP64 iterative refinement on the K_h residual.
+ *
+ * Conventions
+ *   - Every matrix passed as a plain pointer is dense FP64.  Time matrices
+ *     (N_t x N_t) are row-major with row = test index l and column = ansatz
+ *     index k, as in the definitions of Sec. 2.
+ *   - A space-time coefficient block U (or load F~) is M_x x N_t in
+ *     column-major order: U[i + M_x k] is the coefficient of psi_i(x) phi_k(t),
+ *     so that u = vec(U) as in Sec. 3.1.  Several right-hand sides are stored
+ *     one block after the other ([rhs][k][i]).
+ *   - Pointers named *_dev are device (HIP) pointers; all others are host.
+ *   - hip_stream arguments are hipStream_t values passed as void* (NULL =
+ *     the null stream).  Device work is ordered on that stream.
+ *   - Return value: STFD_OK (0) or a negative STFD_E* code; the message of
+ *     the last error of the calling thread is returned by stfd_last_error().
+ *     Nothing aborts the process.  On error, outputs are left unspecified
+ *     unless stated otherwise, and handles stay valid.
+ *   - The caller owns all buffers it passes; the library owns the opaque
+ *     handles and everything they hold until the matching *_free.
+ */
+#ifndef STFD_H
+#define STFD_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STFD_OK 0
+#define STFD_EINVAL (-1)   /* invalid argument (null pointer, bad size, bad mesh) */
+#define STFD_ENOMEM (-2)   /* host or device allocation failed, or size overflow */
+#define STFD_EHIP (-3)     /* a HIP runtime call failed */
+#define STFD_ENUMERIC (-4) /* A_t not SPD, Re(lambda) <= 0, zero/non-finite pivot, NaN input */
+#define STFD_ENOCONV (-5)  /* refinement did not reach rtol within max_refine */
+#define STFD_ESTATE (-6)   /* call out of order (e.g. solve before factor) */
+
+#define STFD_PREC_FP64 0   /* every step in (complex) FP64 */
+#define STFD_PREC_FP32 1   /* factor, sweeps, second forward and back transform in
+                              complex FP32 with FP32 accumulation; residual and
+                              update in FP64 */
+
+#define STFD_MAX_HIST 64
+
+typedef struct stfd_space stfd_space;
+typedef struct stfd_problem stfd_problem;
+typedef struct stfd_batch stfd_batch;
+
+typedef struct {
+    int precision;        /* STFD_PREC_FP64 or STFD_PREC_FP32 (default FP32) */
+    int fwd_fp64;         /* FP32 precision only: run the first forward GEMM
+                             (F^ A_t^-1 conj(U_t) Sigma^-1) in FP64 (1, default)
+                             or in FP32 (0) */
+    double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
+    int max_refine;       /* maximum number of refinement corrections (default 30) */
+} stfd_opts;
+
+typedef struct {
+    double min_re_lambda; /* min_k Re(lambda_k) */
+    double max_abs_lambda;
+    double sigma_min;     /* singular values of X with unit 2-norm columns */
+    double sigma_max;
+    double kappa2;        /* sigma_max / sigma_min */
+    double eig_residual;  /* max_k ||M_t x_k - lambda_k A_t x_k|| / ((||M_t|| + |lambda_k| ||A_t||) ||x_k||) */
+    int n_real;           /* real eigenvalues */
+    int n_pairs;          /* conjugate pairs */
+    int n_sys;            /* spatial systems solved per application: n_real + n_pairs */
+    int half_band;        /* half-bandwidth of the spatial matrices */
+    double setup_seconds; /* host time of the decomposition and uploads */
+    double factor_bytes;  /* device bytes of the stored band factors */
+} stfd_setup_report;
+
+typedef struct {
+    int iterations;       /* FD applications performed (1 = no correction) */
+    int converged;        /* 1 if rel_residual[iterations-1] <= rtol */
+    int nrhs;
+    double rel_residual[STFD_MAX_HIST]; /* after each application, max over RHS */
+    double seconds;       /* wall time of the call, including the final sync */
+} stfd_solve_report;
+
+/* Fills *o with the defaults listed above. */
+int stfd_opts_default(stfd_opts* o);
+
+/* Message of the last error on this thread ("" if none).  Never NULL. */
+const char* stfd_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * Time matrices (Sec. 2): for the hats phi_1..phi_Nt on 0 = t_0 < ... < t_Nt = T
+ * and the element indicators chi_l,
+ *   Mt[l,k] = <phi_k, H_T phi_l>,  At[l,k] = <phi_k', H_T phi_l>,
+ *   Ct[k,l] = <chi_l, H_T phi_k>.
+ * t: Nt+1 strictly increasing nodes with t[0] = 0.  At, Mt, Ct: caller-owned
+ * Nt*Nt row-major outputs; Ct may be NULL.  Computed from the summed
+ * H_T series (a log-tan kernel) with singularity-aware quadrature to about
+ * 1e-14 relative accuracy.  Host only; needs no GPU.
+ * Errors: STFD_EINVAL (Nt < 1, t not increasing, null output).
+ * ------------------------------------------------------------------------- */
+int stfd_assemble_time(int Nt, const double* t, double* At, double* Mt, double* Ct);
+
+/* ---------------------------------------------------------------------------
+ * Spatial discretisation (Sec. 2): P1 hats psi_i on a triangulation.
+ *   xy : 2*nv vertex coordinates (x0, y0, x1, y1, ...)
+ *   tri: 3*ntri vertex indices, counter-clockwise
+ *   dof: nv interior-node numbers 0..M_x-1, or -1 for Dirichlet vertices;
+ *        every number 0..M_x-1 must occur exactly once.
+ * Builds M_x[i,j] = <psi_j, psi_i>, A_x[i,j] = <grad psi_j, grad psi_i> and
+ * M10[i,j] = <chi_j, psi_i> (the M_{h_x}^{1,0} of Sec. 2) in CSR form, and
+ * the half-bandwidth b = max |i-j| over the nonzeros of M_x and A_x.
+ * The handle copies everything it needs.  Host only.
+ * Errors: STFD_EINVAL (bad indices, clockwise or degenerate triangle),
+ *         STFD_ENOMEM.
+ * ------------------------------------------------------------------------- */
+int stfd_space_create(int nv, const double* xy, int ntri, const int* tri, const int* dof,
+                      stfd_space** out);
+void stfd_space_free(stfd_space* s);
+
+/* M_x (number of interior nodes), N_x (triangles), half-bandwidth, and the
+ * number of nonzeros of M_x (= of A_x; the union pattern).  Any output may
+ * be NULL. */
+int stfd_space_info(const stfd_space* s, int* Mx, int* Ntri, int* half_band, long long* nnz);
+
+/* CSR export.  which: 0 = M_x, 1 = A_x (both M_x x M_x, nnz entries, shared
+ * pattern), 2 = M10 (M_x x N_x, 3 entries per triangle at most).
+ * rowptr: rows+1 ints, col/val: nnz entries (query sizes with
+ * stfd_space_csr_size).  Host only. */
+int stfd_space_csr_size(const stfd_space* s, int which, int* rows, int* cols, long long* nnz);
+int stfd_space_export_csr(const stfd_space* s, int which, int* rowptr, int* col, double* val);
+
+/* ---------------------------------------------------------------------------
+ * Right-hand side (Sec. 2): f is replaced by its mean on every prism
+ * omega_j x (t_{l-1}, t_l), and the load is F~ = M10 F Ct^T.
+ *
+ * stfd_project_f: F[j + Ntri*l] = mean of f over triangle j x element l for
+ *   kind 0: f = sum_q c_q sin(a_q pi xi1) sin(b_q pi xi2) cos(d_q pi t / T)
+ *   kind 1: f = sum_q c_q sin(a_q pi xi1) sin(b_q pi xi2) (2t + 2 pi^2 t^2)
+ *           (kind 1 with a = b = 1, c = 1 on the unit square is the load of
+ *           u = sin(pi x1) sin(pi x2) t^2)
+ * with xi = (x - (xmin, ymin)) / (xmax - xmin, ymax - ymin) and box =
+ * {xmin, xmax, ymin, ymax}.  Space means use a 10x10 collapsed Gauss rule per
+ * triangle, time means are exact.  F: caller-owned Ntri*Nt, column-major.
+ * stfd_assemble_load: Ftilde = M10 F Ct^T, Ftilde caller-owned M_x*Nt
+ * column-major; Ct row-major as returned by stfd_assemble_time.  Host only.
+ * ------------------------------------------------------------------------- */
+int stfd_project_f(const stfd_space* s, int Nt, const double* t, int kind, int nmodes,
+                   const int* a, const int* b, const int* d, const double* c,
+                   const double* box, double* F);
+int stfd_assemble_load(const stfd_space* s, int Nt, const double* Ct, const double* F,
+                       double* Ftilde);
+
+/* ---------------------------------------------------------------------------
+ * Steps 1a/1b of Algorithm FD on the host, for tests and reports.
+ * Computes the generalised eigenvalues of (Mt, At) (Cholesky of At, Hessenberg
+ * reduction, shifted QR), eigenvectors with unit 2-norm columns arranged as
+ * [pairs with Im > 0 | their exact conjugates | real ones], and the singular
+ * values of that X (one-sided Jacobi).  Outputs (caller-owned, any may be
+ * NULL): lam_re/lam_im (Nt), X_re/X_im (Nt*Nt row-major: X[row*Nt + col],
+ * column = eigenvector), sigma (Nt, descending), rep.
+ * Errors: STFD_EINVAL, STFD_ENUMERIC (At not SPD, QR did not converge,
+ * Re(lambda) <= 0).  Host only.
+ * ------------------------------------------------------------------------- */
+int stfd_time_decompose(int Nt, const double* At, const double* Mt, double* lam_re,
+                        double* lam_im, double* X_re, double* X_im, double* sigma,
+                        stfd_setup_report* rep);
+
+/* ---------------------------------------------------------------------------
+ * stfd_fd_setup: steps 1a/1b for the pencil (Mt, At) on the host in FP64,
+ * plus the transform factors of steps 2 and 4, uploaded to the current HIP
+ * device on hip_stream.  Copies At and Mt; space must outlive the problem.
+ * opts may be NULL (defaults).
+ * Errors: STFD_EINVAL, STFD_ENUMERIC, STFD_ENOMEM, STFD_EHIP.
+ * ------------------------------------------------------------------------- */
+int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, const double* Mt,
+                  const stfd_opts* opts, void* hip_stream, stfd_problem** out);
+int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* rep);
+
+/* ---------------------------------------------------------------------------
+ * stfd_fd_factor: step 3, first half.  For every system k (one per
+ * conjugate pair, Im(lambda_k) > 0, and one per real eigenvalue) factors
+ *     M_x + lambda_k A_x = L_k D_k L_k^T
+ * (complex symmetric: transpose, not conjugate transpose; no pivoting) in
+ * band form of half-bandwidth b, on the device, in the precision of the
+ * options.  Stream-ordered; no host synchronisation.  Calling it again
+ * refactors.
+ * Errors: STFD_ESTATE (no setup), STFD_ENOMEM, STFD_EHIP.  A zero or
+ * non-finite pivot is reported by the next stfd_fd_solve as STFD_ENUMERIC.
+ * ------------------------------------------------------------------------- */
+int stfd_fd_factor(stfd_problem* p, void* hip_stream);
+
+/* ---------------------------------------------------------------------------
+ * stfd_fd_solve: steps 2-4 and FP64 refinement.
+ *   F_dev: nrhs loads F~ (device FP64, [rhs][k][i], M_x*Nt each), read only
+ *   U_dev: nrhs solutions (device FP64, same layout), overwritten
+ * Iterates u <- u + FD(F~ - K_h u) until the relative residual of every RHS
+ * is <= rtol or max_refine corrections were made.  Synchronises hip_stream
+ * once per iteration to read the residual norms (a few bytes).  rep may be
+ * NULL.  Work buffers are allocated on first use and kept for later calls
+ * with up to the same nrhs.
+ * Errors: STFD_ESTATE (not factored), STFD_EINVAL, STFD_ENUMERIC (zero or
+ * non-finite pivot, non-finite residual), STFD_ENOCONV (rtol not reached;
+ * U_dev then holds the last iterate), STFD_ENOMEM, STFD_EHIP.
+ * ------------------------------------------------------------------------- */
+int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, double* U_dev,
+                  stfd_solve_report* rep, void* hip_stream);
+
+/* K_h applied on the device: R_dev = F_dev - K_h U_dev for nrhs blocks, and
+ * the squared 2-norms of every R and F block in norms[2*nrhs] (host, may be
+ * NULL; when given the call synchronises hip_stream).  Used by the solve and
+ * exposed for tests (Kronecker identity of Sec. 3.1). */
+int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, const double* U_dev,
+                     double* R_dev, double* norms, void* hip_stream);
+
+void stfd_problem_free(stfd_problem* p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STFD_H */

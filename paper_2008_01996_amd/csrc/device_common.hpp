@@ -1,0 +1,78 @@
+// Device helpers for gfx950 (CDNA4): complex arithmetic on real pairs and the
+// 16x16x4 matrix-core (MFMA) instructions in FP32 and FP64.
+//
+// MFMA 16x16x4 operand layout (wave of 64 lanes, one 16x16 output block):
+//   A operand: lane l holds A[m = l % 16][k = l / 16]
+//   B operand: lane l holds B[k = l / 16][n = l % 16]
+//   D output : lane l holds D[m = 4 * (l / 16) + j][n = l % 16], j = 0..3
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace stfd {
+
+template <typename T>
+struct cplx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cinv(cplx<T> a) {
+    // 1/a with a scaling that avoids overflow in |a|^2
+    const T s = fabs(a.re) > fabs(a.im) ? fabs(a.re) : fabs(a.im);
+    const T ar = a.re / s, ai = a.im / s;
+    const T d = (ar * ar + ai * ai) * s;
+    return {ar / d, -ai / d};
+}
+
+template <typename T>
+struct vec4;
+template <>
+struct vec4<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct vec4<double> {
+    typedef double type __attribute__((ext_vector_type(4)));
+};
+
+template <typename T>
+__device__ __forceinline__ typename vec4<T>::type mfma16x16x4(T a, T b, typename vec4<T>::type c);
+
+template <>
+__device__ __forceinline__ vec4<float>::type mfma16x16x4<float>(float a, float b, vec4<float>::type c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <>
+__device__ __forceinline__ vec4<double>::type mfma16x16x4<double>(double a, double b, vec4<double>::type c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+__device__ __forceinline__ typename vec4<T>::type zero4() {
+    typename vec4<T>::type z;
+    z[0] = z[1] = z[2] = z[3] = T(0);
+    return z;
+}
+
+// block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024)
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) scratch[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += scratch[w];
+    }
+    __syncthreads();
+    return s;
+}
+
+}  // namespace stfd

@@ -1,0 +1,349 @@
+// Dense FP64 host linear algebra for the FD setup; see host_linalg.hpp.
+#include "host_linalg.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <limits>
+
+namespace stfd {
+
+bool cholesky(int n, std::vector<double>& a) {
+    for (int j = 0; j < n; ++j) {
+        double d = a[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= a[(size_t)j * n + k] * a[(size_t)j * n + k];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        d = std::sqrt(d);
+        a[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double s = a[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= a[(size_t)i * n + k] * a[(size_t)j * n + k];
+            a[(size_t)i * n + j] = s / d;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = i + 1; j < n; ++j) a[(size_t)i * n + j] = 0.0;
+    return true;
+}
+
+template <typename T>
+static void fwd_impl(int n, const std::vector<double>& L, T* b, int nrhs) {
+    for (int i = 0; i < n; ++i) {
+        T* bi = b + (size_t)i * nrhs;
+        for (int k = 0; k < i; ++k) {
+            const double l = L[(size_t)i * n + k];
+            const T* bk = b + (size_t)k * nrhs;
+            for (int r = 0; r < nrhs; ++r) bi[r] -= l * bk[r];
+        }
+        const double d = L[(size_t)i * n + i];
+        for (int r = 0; r < nrhs; ++r) bi[r] /= d;
+    }
+}
+
+template <typename T>
+static void bwd_impl(int n, const std::vector<double>& L, T* b, int nrhs) {
+    for (int i = n - 1; i >= 0; --i) {
+        T* bi = b + (size_t)i * nrhs;
+        for (int k = i + 1; k < n; ++k) {
+            const double l = L[(size_t)k * n + i];
+            const T* bk = b + (size_t)k * nrhs;
+            for (int r = 0; r < nrhs; ++r) bi[r] -= l * bk[r];
+        }
+        const double d = L[(size_t)i * n + i];
+        for (int r = 0; r < nrhs; ++r) bi[r] /= d;
+    }
+}
+
+void chol_forward(int n, const std::vector<double>& L, double* b, int nrhs) { fwd_impl(n, L, b, nrhs); }
+void chol_backward(int n, const std::vector<double>& L, double* b, int nrhs) { bwd_impl(n, L, b, nrhs); }
+void chol_forward(int n, const std::vector<double>& L, cd* b, int nrhs) { fwd_impl(n, L, b, nrhs); }
+void chol_backward(int n, const std::vector<double>& L, cd* b, int nrhs) { bwd_impl(n, L, b, nrhs); }
+
+// ---------------------------------------------------------------------------
+// Householder reduction to upper Hessenberg form, H = Q^T A Q.
+// ---------------------------------------------------------------------------
+static void hessenberg(int n, std::vector<double>& a, std::vector<double>& q) {
+    q.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) q[(size_t)i * n + i] = 1.0;
+    std::vector<double> v(n);
+    for (int k = 0; k + 2 < n; ++k) {
+        double alpha = 0.0;
+        for (int i = k + 1; i < n; ++i) alpha += a[(size_t)i * n + k] * a[(size_t)i * n + k];
+        alpha = std::sqrt(alpha);
+        if (alpha == 0.0) continue;
+        const double x0 = a[(size_t)(k + 1) * n + k];
+        if (x0 > 0) alpha = -alpha;             // v = x - alpha e1, alpha = -sign(x0)|x|
+        double vnorm2 = 0.0;
+        for (int i = k + 1; i < n; ++i) {
+            v[i] = a[(size_t)i * n + k];
+        }
+        v[k + 1] -= alpha;
+        for (int i = k + 1; i < n; ++i) vnorm2 += v[i] * v[i];
+        if (vnorm2 == 0.0) continue;
+        const double beta = 2.0 / vnorm2;
+        // A <- (I - beta v v^T) A   (rows k+1..n-1)
+        for (int j = k; j < n; ++j) {
+            double s = 0.0;
+            for (int i = k + 1; i < n; ++i) s += v[i] * a[(size_t)i * n + j];
+            s *= beta;
+            for (int i = k + 1; i < n; ++i) a[(size_t)i * n + j] -= s * v[i];
+        }
+        // A <- A (I - beta v v^T)   (columns k+1..n-1)
+        for (int i = 0; i < n; ++i) {
+            double* ai = &a[(size_t)i * n];
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += ai[j] * v[j];
+            s *= beta;
+            for (int j = k + 1; j < n; ++j) ai[j] -= s * v[j];
+        }
+        // Q <- Q (I - beta v v^T)
+        for (int i = 0; i < n; ++i) {
+            double* qi = &q[(size_t)i * n];
+            double s = 0.0;
+            for (int j = k + 1; j < n; ++j) s += qi[j] * v[j];
+            s *= beta;
+            for (int j = k + 1; j < n; ++j) qi[j] -= s * v[j];
+        }
+        for (int i = k + 2; i < n; ++i) a[(size_t)i * n + k] = 0.0;
+    }
+}
+
+static inline double cabs1(cd z) { return std::fabs(z.real()) + std::fabs(z.imag()); }
+
+// Unitary plane rotation G = [[c, s], [-conj(s), c]] with G [x; y] = [r; 0].
+static inline void givens(cd x, cd y, double& c, cd& s) {
+    const double ay = std::abs(y);
+    if (ay == 0.0) { c = 1.0; s = 0.0; return; }
+    const double ax = std::abs(x);
+    if (ax == 0.0) { c = 0.0; s = std::conj(y) / ay; return; }
+    const double r = std::hypot(ax, ay);
+    c = ax / r;
+    s = (x / ax) * std::conj(y) / r;
+}
+
+// ---------------------------------------------------------------------------
+// Single-shift complex QR on an upper Hessenberg matrix, full Schur form
+// T = Z^H H Z accumulated into z.  Wilkinson shifts, exceptional shifts every
+// ten iterations without deflation.
+// ---------------------------------------------------------------------------
+static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::string* err) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    double hnorm = 0.0;
+    for (auto& x : h) hnorm = std::max(hnorm, cabs1(x));
+    const double small = std::max(hnorm, 1.0) * std::numeric_limits<double>::min() / eps;
+    int ihi = n - 1;
+    int iter = 0, total = 0;
+    while (ihi > 0) {
+        int l = ihi;
+        for (; l > 0; --l) {
+            const cd sub = h[(size_t)l * n + l - 1];
+            double tst = cabs1(h[(size_t)(l - 1) * n + l - 1]) + cabs1(h[(size_t)l * n + l]);
+            if (tst == 0.0) tst = hnorm;
+            if (cabs1(sub) <= eps * tst || cabs1(sub) <= small) {
+                h[(size_t)l * n + l - 1] = 0.0;
+                break;
+            }
+        }
+        if (l == ihi) {            // 1x1 block deflated
+            --ihi;
+            iter = 0;
+            continue;
+        }
+        ++iter;
+        if (++total > 60 * n) {
+            if (err) *err = "complex QR iteration did not converge";
+            return false;
+        }
+        cd mu;
+        const cd a = h[(size_t)(ihi - 1) * n + ihi - 1];
+        const cd b = h[(size_t)(ihi - 1) * n + ihi];
+        const cd c = h[(size_t)ihi * n + ihi - 1];
+        const cd d = h[(size_t)ihi * n + ihi];
+        if (iter % 10 == 0) {
+            mu = d + 0.75 * std::abs(c);          // exceptional shift
+        } else {
+            // eigenvalue of [[a, b], [c, d]] closest to d
+            const cd tr2 = 0.5 * (a - d);
+            const cd disc = std::sqrt(tr2 * tr2 + b * c);
+            const cd e1 = 0.5 * (a + d) + disc;
+            const cd e2 = 0.5 * (a + d) - disc;
+            mu = (std::abs(e1 - d) < std::abs(e2 - d)) ? e1 : e2;
+        }
+        // shifted QR sweep on rows/columns l..ihi by a chase of rotations
+        cd x = h[(size_t)l * n + l] - mu;
+        cd y = h[(size_t)(l + 1) * n + l];
+        for (int k = l; k < ihi; ++k) {
+            if (k > l) {
+                x = h[(size_t)k * n + k - 1];
+                y = h[(size_t)(k + 1) * n + k - 1];
+            }
+            double cs;
+            cd sn;
+            givens(x, y, cs, sn);
+            // rows k, k+1 from column max(k-1, l) to n-1
+            const int j0 = (k > l) ? k - 1 : l;
+            cd* rk = &h[(size_t)k * n];
+            cd* rk1 = &h[(size_t)(k + 1) * n];
+            for (int j = j0; j < n; ++j) {
+                const cd u = rk[j], v = rk1[j];
+                rk[j] = cs * u + sn * v;
+                rk1[j] = -std::conj(sn) * u + cs * v;
+            }
+            if (k > l) h[(size_t)(k + 1) * n + k - 1] = 0.0;
+            // columns k, k+1 (times G^H) for rows 0..min(k+2, ihi)
+            const int i1 = std::min(k + 2, ihi);
+            const cd snc = std::conj(sn);
+            for (int i = 0; i <= i1; ++i) {
+                cd* ri = &h[(size_t)i * n];
+                const cd u = ri[k], v = ri[k + 1];
+                ri[k] = cs * u + snc * v;
+                ri[k + 1] = -sn * u + cs * v;
+            }
+            for (int i = 0; i < n; ++i) {
+                cd* zi = &z[(size_t)i * n];
+                const cd u = zi[k], v = zi[k + 1];
+                zi[k] = cs * u + snc * v;
+                zi[k + 1] = -sn * u + cs * v;
+            }
+        }
+    }
+    return true;
+}
+
+bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<cd>& vecs,
+              std::string* err) {
+    std::vector<double> q;
+    hessenberg(n, a, q);
+    std::vector<cd> h((size_t)n * n), z((size_t)n * n);
+    for (size_t i = 0; i < h.size(); ++i) {
+        h[i] = a[i];
+        z[i] = q[i];
+    }
+    if (!schur_complex(n, h, z, err)) return false;
+    vals.resize(n);
+    for (int k = 0; k < n; ++k) vals[k] = h[(size_t)k * n + k];
+    // eigenvectors of the triangular T: (T - t_kk I) v = 0, v_k = 1
+    double tnorm = 0.0;
+    for (auto& x : h) tnorm = std::max(tnorm, cabs1(x));
+    const double smin = std::max(std::numeric_limits<double>::epsilon() * tnorm,
+                                 std::numeric_limits<double>::min());
+    std::vector<cd> v(n);
+    vecs.assign((size_t)n * n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        std::fill(v.begin(), v.end(), cd(0.0));
+        v[k] = 1.0;
+        const cd tkk = h[(size_t)k * n + k];
+        for (int i = k - 1; i >= 0; --i) {
+            cd s = 0.0;
+            const cd* ti = &h[(size_t)i * n];
+            for (int j = i + 1; j <= k; ++j) s += ti[j] * v[j];
+            cd den = ti[i] - tkk;
+            if (cabs1(den) < smin) den = smin;
+            v[i] = -s / den;
+            // rescale to avoid overflow on badly separated eigenvalues
+            if (cabs1(v[i]) > 1e150) {
+                for (int j = i; j <= k; ++j) v[j] *= 1e-150;
+            }
+        }
+        // y = Z v
+        for (int i = 0; i < n; ++i) {
+            const cd* zi = &z[(size_t)i * n];
+            cd s = 0.0;
+            for (int j = 0; j <= k; ++j) s += zi[j] * v[j];
+            vecs[(size_t)i * n + k] = s;
+        }
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi SVD.  Columns of a are orthogonalised by plane
+// rotations applied on the right; V accumulates the rotations.  Pairs are
+// visited in a round-robin tournament so that each round's rotations are
+// independent.
+// ---------------------------------------------------------------------------
+bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
+                std::vector<cd>& V, std::string* err) {
+    const double eps = std::numeric_limits<double>::epsilon();
+    // work column-major for contiguous column access
+    std::vector<cd> A((size_t)n * n), W((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)j * n + i] = a[(size_t)i * n + j];
+    for (int j = 0; j < n; ++j) W[(size_t)j * n + j] = 1.0;
+    const int m = n + (n & 1);            // tournament size (pad with a dummy)
+    std::vector<int> ring(m);
+    for (int i = 0; i < m; ++i) ring[i] = i;
+    bool converged = false;
+    for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+        double off = 0.0;
+        for (int round = 0; round < m - 1; ++round) {
+#pragma omp parallel for schedule(static) reduction(max : off)
+            for (int pidx = 0; pidx < m / 2; ++pidx) {
+                int p = ring[pidx], q = ring[m - 1 - pidx];
+                if (p >= n || q >= n) continue;
+                if (p > q) std::swap(p, q);
+                cd* ap = &A[(size_t)p * n];
+                cd* aq = &A[(size_t)q * n];
+                double al = 0.0, be = 0.0;
+                cd ga = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    al += std::norm(ap[i]);
+                    be += std::norm(aq[i]);
+                    ga += std::conj(ap[i]) * aq[i];
+                }
+                const double g = std::abs(ga);
+                if (g == 0.0 || g <= eps * std::sqrt(al * be)) continue;
+                off = std::max(off, g / std::sqrt(al * be));
+                // D = diag(1, e^{-i phi}) makes the Gram matrix real; then a
+                // real Jacobi rotation diagonalises it
+                const cd ph = std::conj(ga) / g;             // e^{-i phi}
+                const double zeta = (be - al) / (2.0 * g);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t);
+                const double sn = c * t;
+                cd* wp = &W[(size_t)p * n];
+                cd* wq = &W[(size_t)q * n];
+                for (int i = 0; i < n; ++i) {
+                    const cd x = ap[i], y = ph * aq[i];
+                    ap[i] = c * x - sn * y;
+                    aq[i] = sn * x + c * y;
+                    const cd xv = wp[i], yv = ph * wq[i];
+                    wp[i] = c * xv - sn * yv;
+                    wq[i] = sn * xv + c * yv;
+                }
+            }
+            // rotate the tournament (element 0 fixed)
+            const int last = ring[m - 1];
+            for (int i = m - 1; i > 1; --i) ring[i] = ring[i - 1];
+            ring[1] = last;
+        }
+        if (off <= 4 * eps) converged = true;
+    }
+    if (!converged) {
+        if (err) *err = "Jacobi SVD did not converge";
+        return false;
+    }
+    std::vector<double> sv(n);
+    for (int j = 0; j < n; ++j) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += std::norm(A[(size_t)j * n + i]);
+        sv[j] = std::sqrt(t);
+    }
+    std::vector<int> order(n);
+    for (int j = 0; j < n; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sv[x] > sv[y]; });
+    s.resize(n);
+    U.assign((size_t)n * n, 0.0);
+    V.assign((size_t)n * n, 0.0);
+    for (int jj = 0; jj < n; ++jj) {
+        const int j = order[jj];
+        s[jj] = sv[j];
+        const double inv = sv[j] > 0 ? 1.0 / sv[j] : 0.0;
+        for (int i = 0; i < n; ++i) {
+            U[(size_t)i * n + jj] = A[(size_t)j * n + i] * inv;
+            V[(size_t)i * n + jj] = W[(size_t)j * n + i];
+        }
+    }
+    return true;
+}
+
+}  // namespace stfd

@@ -1,0 +1,39 @@
+// Dense FP64 host linear algebra for the once-per-problem setup of the FD
+// solver (steps 1a and 1b of Algorithm FD): Cholesky, a nonsymmetric
+// eigensolver (Householder-Hessenberg reduction + shifted complex QR with
+// eigenvectors from the Schur form) and a one-sided Jacobi SVD.
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+namespace stfd {
+
+using cd = std::complex<double>;
+
+// Row-major n x n dense matrices throughout.
+
+// In-place Cholesky A = L L^T (lower triangle of a holds L on return).
+// Returns false if a pivot is not positive and finite.
+bool cholesky(int n, std::vector<double>& a);
+
+// Solves L y = b (lower) and L^T x = y in place for a column-major set of
+// nrhs right-hand sides stored row-major as b[i*nrhs + r].
+void chol_forward(int n, const std::vector<double>& L, double* b, int nrhs);
+void chol_backward(int n, const std::vector<double>& L, double* b, int nrhs);
+void chol_forward(int n, const std::vector<double>& L, cd* b, int nrhs);
+void chol_backward(int n, const std::vector<double>& L, cd* b, int nrhs);
+
+// Eigenvalues and right eigenvectors of a real nonsymmetric matrix a (n x n,
+// row-major, destroyed).  Returns false if the QR iteration does not
+// converge.  vecs[i*n + k] = component i of eigenvector k (unnormalised).
+bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<cd>& vecs,
+              std::string* err);
+
+// One-sided Jacobi SVD of a complex n x n matrix: a = U diag(s) V^H.
+// a is row-major and destroyed; U, V row-major; s descending.
+bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
+                std::vector<cd>& V, std::string* err);
+
+}  // namespace stfd

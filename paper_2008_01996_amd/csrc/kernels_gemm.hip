@@ -1,0 +1,206 @@
+// Dense transforms of Algorithm FD (steps 2 and 4, Sec. 4.4) and the FP64
+// residual of the refinement, as matrix-core (MFMA) GEMMs, plus the sparse
+// spatial operator and small helpers.
+//
+// Every GEMM here has the shape  C (M x N) = A (M x K) * B (K x N)  with
+//   A column-major (the space-time block, M = M_x rows, i fastest),
+//   B row-major and shared by the batch (the small time-side factor),
+//   C column-major,
+// batched over right-hand sides.  M is large (1e4..1e5) and N, K <= 2 N_t.
+// A 64 x 64 output tile per workgroup, 4 waves of 32 x 32, K in steps of 16
+// staged through LDS; each wave issues 16x16x4 MFMAs with the B tile as the
+// first operand so that the output lane index runs along M (coalesced
+// column-major stores).
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace stfd {
+
+constexpr int BM = 64, BN = 64, BK = 16;
+
+template <typename TA, typename TC, int EPI>
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
+    __shared__ TC As[BK][BM];
+    __shared__ TC Bs[BK][BN];
+    __shared__ double red[8];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int batch = blockIdx.z;
+    const TA* A = static_cast<const TA*>(g.A) + (size_t)batch * g.strideA;
+    const TC* B = static_cast<const TC*>(g.B);
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
+
+    typename vec4<TC>::type acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = zero4<TC>();
+
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        // A tile: 64 rows (m) x 16 (k), coalesced along m
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m = tid & 63, k = (tid >> 6) + 4 * i;
+            const int gm = m0 + m, gk = k0 + k;
+            TC v = TC(0);
+            if (gm < g.M && gk < g.K) v = static_cast<TC>(A[(size_t)gm + (size_t)gk * g.lda]);
+            As[k][m] = v;
+        }
+        // B tile: 16 (k) x 64 (n), coalesced along n
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = tid & 63, k = (tid >> 6) + 4 * i;
+            const int gn = n0 + n, gk = k0 + k;
+            TC v = TC(0);
+            if (gn < g.N && gk < g.K) v = B[(size_t)gk * g.ldb + gn];
+            Bs[k][n] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const int k = 4 * kk + lk;
+            TC bf[2], af[2];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) bf[t] = Bs[k][wn + 16 * t + li];
+#pragma unroll
+            for (int t = 0; t < 2; ++t) af[t] = As[k][wm + 16 * t + li];
+#pragma unroll
+            for (int tn = 0; tn < 2; ++tn)
+#pragma unroll
+                for (int tm = 0; tm < 2; ++tm) acc[tn][tm] = mfma16x16x4<TC>(bf[tn], af[tm], acc[tn][tm]);
+        }
+        __syncthreads();
+    }
+
+    // epilogue: acc[tn][tm][j] = C[m = m0 + wm + 16 tm + li][n = n0 + wn + 16 tn + 4 lk + j]
+    double s_r = 0.0, s_f = 0.0;
+#pragma unroll
+    for (int tn = 0; tn < 2; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = m0 + wm + 16 * tm + li;
+                const int n = n0 + wn + 16 * tn + 4 * lk + j;
+                if (m >= g.M || n >= g.N) continue;
+                const size_t off = (size_t)batch * g.strideC + (size_t)m + (size_t)n * g.ldc;
+                const TC v = acc[tn][tm][j];
+                if (EPI == EPI_STORE_F32) {
+                    static_cast<float*>(g.C)[off] = static_cast<float>(v);
+                } else if (EPI == EPI_STORE_F64) {
+                    static_cast<double*>(g.C)[off] = static_cast<double>(v);
+                } else if (EPI == EPI_ADD_F64) {
+                    static_cast<double*>(g.C)[off] += g.alpha * static_cast<double>(v);
+                } else {   // EPI_RESID: C = F - A B, sums of squares of C and F
+                    const size_t foff = (size_t)batch * g.strideF + (size_t)m + (size_t)n * g.ldc;
+                    const double f = static_cast<const double*>(g.F)[foff];
+                    const double r = f - static_cast<double>(v);
+                    static_cast<double*>(g.C)[off] = r;
+                    s_r += r * r;
+                    s_f += f * f;
+                }
+            }
+    if (EPI == EPI_RESID) {
+        const double tr = block_sum(s_r, red);
+        const double tf = block_sum(s_f, red);
+        if (tid == 0) {
+            const size_t blocks = (size_t)gridDim.x * gridDim.y;
+            const size_t idx = (size_t)batch * blocks + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+            g.partial[2 * idx] = tr;
+            g.partial[2 * idx + 1] = tf;
+        }
+    }
+}
+
+template <typename TA, typename TC, int EPI>
+static hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t st) {
+    dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
+    hipLaunchKernelGGL((gemm_kernel<TA, TC, EPI>), grid, dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(GemmKind kind, const GemmArgs& g, hipStream_t st) {
+    switch (kind) {
+        case GEMM_D_D_STORE_D: return launch_gemm_t<double, double, EPI_STORE_F64>(g, st);
+        case GEMM_D_D_STORE_F: return launch_gemm_t<double, double, EPI_STORE_F32>(g, st);
+        case GEMM_D_F_STORE_F: return launch_gemm_t<double, float, EPI_STORE_F32>(g, st);
+        case GEMM_F_F_STORE_F: return launch_gemm_t<float, float, EPI_STORE_F32>(g, st);
+        case GEMM_F_F_ADD_D: return launch_gemm_t<float, float, EPI_ADD_F64>(g, st);
+        case GEMM_D_D_ADD_D: return launch_gemm_t<double, double, EPI_ADD_F64>(g, st);
+        case GEMM_D_D_RESID: return launch_gemm_t<double, double, EPI_RESID>(g, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+size_t gemm_resid_partials(int M, int N, int batch) {
+    return (size_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+}
+
+// ---------------------------------------------------------------------------
+// Spatial operator for the residual: P[:, j] = M_x U[:, j] and
+// P[:, N_t + j] = A_x U[:, j] (CSR, FP64), for every RHS.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, const int* __restrict__ rowptr,
+                                                            const int* __restrict__ col,
+                                                            const double* __restrict__ valM,
+                                                            const double* __restrict__ valA,
+                                                            const double* __restrict__ U, double* __restrict__ P) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;             // 0..2 Nt-1
+    const int batch = blockIdx.z;
+    if (i >= Mx) return;
+    const int k = j < Nt ? j : j - Nt;
+    const double* val = j < Nt ? valM : valA;
+    const double* u = U + (size_t)batch * Mx * Nt + (size_t)k * Mx;
+    double s = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * u[col[e]];
+    P[(size_t)batch * Mx * 2 * Nt + (size_t)j * Mx + i] = s;
+}
+
+hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, const int* col, const double* valM,
+                                const double* valA, const double* U, double* P, hipStream_t st) {
+    dim3 grid((Mx + 255) / 256, 2 * Nt, nrhs);
+    hipLaunchKernelGGL(spatial_apply_kernel, grid, dim3(256), 0, st, Mx, Nt, rowptr, col, valM, valA, U, P);
+    return hipGetLastError();
+}
+
+// fixed-order reduction of the residual GEMM partial sums: norms[2 r] =
+// ||R_r||^2, norms[2 r + 1] = ||F_r||^2
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, size_t blocks, double* __restrict__ norms) {
+    __shared__ double red[8];
+    const int batch = blockIdx.x;
+    double a = 0.0, b = 0.0;
+    for (size_t q = threadIdx.x; q < blocks; q += blockDim.x) {
+        a += partial[2 * ((size_t)batch * blocks + q)];
+        b += partial[2 * ((size_t)batch * blocks + q) + 1];
+    }
+    a = block_sum(a, red);
+    b = block_sum(b, red);
+    if (threadIdx.x == 0) {
+        norms[2 * batch] = a;
+        norms[2 * batch + 1] = b;
+    }
+}
+
+hipError_t launch_reduce_partials(const double* partial, size_t blocks, int nrhs, double* norms, hipStream_t st) {
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(nrhs), dim3(256), 0, st, partial, blocks, norms);
+    return hipGetLastError();
+}
+
+__global__ void fill_zero_kernel(double* __restrict__ p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace stfd

@@ -1,0 +1,583 @@
+// C-ABI of the FD solver: setup (steps 1a/1b and the transform factors),
+// band factorization and the refined solve on one GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "host_internal.hpp"
+#include "host_linalg.hpp"
+#include "kernels.hpp"
+
+using stfd::cd;
+using stfd::fail;
+
+struct stfd_problem {
+    const stfd_space* space = nullptr;
+    stfd_opts opts{};
+    int Nt = 0, Mx = 0, b = 0, bp = 0, nsys = 0, npair = 0, nreal = 0;
+    stfd_setup_report rep{};
+    std::vector<double> lam_sys;   // 2 nsys (re, im)
+    bool factored = false;
+    // device data
+    int* d_rowptr = nullptr;
+    int* d_col = nullptr;
+    double* d_valM = nullptr;
+    double* d_valA = nullptr;
+    double* d_lam = nullptr;
+    double* d_W1 = nullptr;     // Nt x 2Nt  FP64: [Re | Im] of A_t^-1 conj(U_t) Sigma^-1
+    float* d_W1f = nullptr;     // FP32 copy (fwd_fp64 = 0)
+    void* d_W2 = nullptr;       // 2Nt x 2nsys  [[Re, Im], [-Im, Re]] of V_t^T[:, sys]
+    void* d_Xb = nullptr;       // 2nsys x Nt   [Re; -Im] of c_k x_k^T
+    double* d_Bres = nullptr;   // 2Nt x Nt     [A_t^T; M_t^T]
+    void* d_LB = nullptr;       // band factors
+    int* d_flag = nullptr;
+    // work buffers, sized for nrhs_cap right-hand sides
+    int nrhs_cap = 0;
+    void* d_T1 = nullptr;       // Mx x 2Nt per RHS (FP32 or FP64)
+    void* d_G = nullptr;        // Mx x 2nsys per RHS
+    double* d_P = nullptr;      // Mx x 2Nt per RHS
+    double* d_R = nullptr;      // Mx x Nt per RHS
+    double* d_part = nullptr;
+    double* d_norms = nullptr;
+};
+
+namespace {
+
+bool is_fp32(const stfd_problem* p) { return p->opts.precision == STFD_PREC_FP32; }
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(STFD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(e_, what);     \
+    } while (0)
+
+template <typename T>
+int upload(T** dst, const void* src, size_t bytes, hipStream_t st) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 16));
+    if (e != hipSuccess) return fail(STFD_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+    *dst = static_cast<T*>(p);
+    e = hipMemcpyAsync(p, src, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    return STFD_OK;
+}
+
+void free_work(stfd_problem* p) {
+    (void)hipFree(p->d_T1);
+    (void)hipFree(p->d_G);
+    (void)hipFree(p->d_P);
+    (void)hipFree(p->d_R);
+    (void)hipFree(p->d_part);
+    (void)hipFree(p->d_norms);
+    p->d_T1 = p->d_G = nullptr;
+    p->d_P = p->d_R = p->d_part = p->d_norms = nullptr;
+    p->nrhs_cap = 0;
+}
+
+struct Decomp {
+    int n = 0, npair = 0, nreal = 0;
+    std::vector<cd> lam;   // n, ordered [pairs Im>0 | conjugates | real]
+    std::vector<cd> X;     // n x n row-major, unit 2-norm columns
+    std::vector<cd> U, V;  // SVD X = U diag(s) V^H
+    std::vector<double> s;
+    std::vector<double> L; // Cholesky factor of A_t
+    double eig_res = 0.0;
+};
+
+int decompose(int n, const double* At, const double* Mt, Decomp& D) {
+    D.n = n;
+    for (size_t i = 0; i < (size_t)n * n; ++i)
+        if (!std::isfinite(At[i]) || !std::isfinite(Mt[i])) return fail(STFD_ENUMERIC, "non-finite time matrix");
+    D.L.assign(At, At + (size_t)n * n);
+    if (!stfd::cholesky(n, D.L)) return fail(STFD_ENUMERIC, "A_t is not symmetric positive definite");
+    // C = L^-1 M_t L^-T  (M_t x = lambda A_t x  <=>  C y = lambda y, x = L^-T y)
+    std::vector<double> C(Mt, Mt + (size_t)n * n);
+    stfd::chol_forward(n, D.L, C.data(), n);           // L^-1 M_t  (columns as RHS)
+    // (L^-1 M_t) L^-T = (L^-1 (L^-1 M_t)^T)^T
+    std::vector<double> Ct((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Ct[(size_t)j * n + i] = C[(size_t)i * n + j];
+    stfd::chol_forward(n, D.L, Ct.data(), n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) C[(size_t)i * n + j] = Ct[(size_t)j * n + i];
+    std::vector<cd> vals, vecs;
+    std::string err;
+    if (!stfd::eig_real(n, C, vals, vecs, &err)) return fail(STFD_ENUMERIC, err);
+    // x = L^-T y
+    stfd::chol_backward(n, D.L, vecs.data(), n);
+    double lmax = 0.0;
+    for (auto& v : vals) lmax = std::max(lmax, std::abs(v));
+    const double tol = 1e-9 * std::max(lmax, 1e-300);
+    std::vector<int> up, re;
+    int ndown = 0;
+    for (int k = 0; k < n; ++k) {
+        if (vals[k].imag() > tol) up.push_back(k);
+        else if (vals[k].imag() < -tol) ++ndown;
+        else re.push_back(k);
+    }
+    if ((int)up.size() != ndown) return fail(STFD_ENUMERIC, "eigenvalues do not pair into conjugates");
+    D.npair = (int)up.size();
+    D.nreal = (int)re.size();
+    D.lam.resize(n);
+    D.X.assign((size_t)n * n, 0.0);
+    auto column = [&](int k, std::vector<cd>& x) {
+        x.resize(n);
+        double nrm = 0.0;
+        for (int i = 0; i < n; ++i) {
+            x[i] = vecs[(size_t)i * n + k];
+            nrm += std::norm(x[i]);
+        }
+        nrm = std::sqrt(nrm);
+        // phase: largest entry real and positive
+        int im = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::abs(x[i]) > std::abs(x[im])) im = i;
+        const cd ph = std::conj(x[im]) / std::abs(x[im]);
+        for (auto& v : x) v *= ph / nrm;
+    };
+    std::vector<cd> x;
+    for (int q = 0; q < D.npair; ++q) {
+        column(up[q], x);
+        D.lam[q] = vals[up[q]];
+        D.lam[D.npair + q] = std::conj(vals[up[q]]);
+        for (int i = 0; i < n; ++i) {
+            D.X[(size_t)i * n + q] = x[i];
+            D.X[(size_t)i * n + D.npair + q] = std::conj(x[i]);
+        }
+    }
+    for (int q = 0; q < D.nreal; ++q) {
+        column(re[q], x);
+        const int k = 2 * D.npair + q;
+        D.lam[k] = vals[re[q]].real();
+        double nrm = 0.0;
+        for (int i = 0; i < n; ++i) nrm += x[i].real() * x[i].real();
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < n; ++i) D.X[(size_t)i * n + k] = x[i].real() / nrm;
+    }
+    // eigen residual  ||M x - lam A x|| / ((||M|| + |lam| ||A||) ||x||)
+    double nA = 0.0, nM = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double ra = 0.0, rm = 0.0;
+        for (int j = 0; j < n; ++j) {
+            ra += std::fabs(At[(size_t)i * n + j]);
+            rm += std::fabs(Mt[(size_t)i * n + j]);
+        }
+        nA = std::max(nA, ra);
+        nM = std::max(nM, rm);
+    }
+    D.eig_res = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double r = 0.0, xn = 0.0;
+        for (int i = 0; i < n; ++i) {
+            cd s = 0.0;
+            for (int j = 0; j < n; ++j) s += (Mt[(size_t)i * n + j] - D.lam[k] * At[(size_t)i * n + j]) * D.X[(size_t)j * n + k];
+            r = std::max(r, std::abs(s));
+            xn = std::max(xn, std::abs(D.X[(size_t)i * n + k]));
+        }
+        D.eig_res = std::max(D.eig_res, r / ((nM + std::abs(D.lam[k]) * nA) * xn));
+    }
+    for (auto& l : D.lam)
+        if (!(l.real() > 0.0)) return fail(STFD_ENUMERIC, "an eigenvalue of (M_t, A_t) has Re <= 0");
+    std::vector<cd> Xw = D.X;
+    if (!stfd::svd_jacobi(n, Xw, D.U, D.s, D.V, &err)) return fail(STFD_ENUMERIC, err);
+    return STFD_OK;
+}
+
+void fill_report(const Decomp& D, stfd_setup_report* r) {
+    double mre = 1e300, mab = 0.0;
+    for (auto& l : D.lam) {
+        mre = std::min(mre, l.real());
+        mab = std::max(mab, std::abs(l));
+    }
+    r->min_re_lambda = mre;
+    r->max_abs_lambda = mab;
+    r->sigma_max = D.s.front();
+    r->sigma_min = D.s.back();
+    r->kappa2 = D.s.front() / D.s.back();
+    r->eig_residual = D.eig_res;
+    r->n_real = D.nreal;
+    r->n_pairs = D.npair;
+    r->n_sys = D.npair + D.nreal;
+}
+
+int ensure_work(stfd_problem* p, int nrhs) {
+    if (nrhs <= p->nrhs_cap) return STFD_OK;
+    free_work(p);
+    const size_t Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
+    const size_t es = is_fp32(p) ? 4 : 8;
+    const size_t parts = std::max(stfd::gemm_resid_partials(p->Mx, p->Nt, nrhs), (size_t)1);
+    struct { void** ptr; size_t bytes; } req[] = {
+        {&p->d_T1, Mx * 2 * Nt * es * nrhs},
+        {&p->d_G, Mx * 2 * ns * es * nrhs},
+        {reinterpret_cast<void**>(&p->d_P), Mx * 2 * Nt * 8 * nrhs},
+        {reinterpret_cast<void**>(&p->d_R), Mx * Nt * 8 * nrhs},
+        {reinterpret_cast<void**>(&p->d_part), parts * 2 * 8},
+        {reinterpret_cast<void**>(&p->d_norms), (size_t)2 * nrhs * 8},
+    };
+    for (auto& r : req) {
+        hipError_t e = hipMalloc(r.ptr, std::max<size_t>(r.bytes, 16));
+        if (e != hipSuccess) {
+            free_work(p);
+            return fail(STFD_ENOMEM, std::string("work buffers: ") + hipGetErrorString(e));
+        }
+    }
+    p->nrhs_cap = nrhs;
+    return STFD_OK;
+}
+
+}  // namespace
+
+extern "C" int stfd_time_decompose(int Nt, const double* At, const double* Mt, double* lam_re, double* lam_im,
+                                   double* X_re, double* X_im, double* sigma, stfd_setup_report* rep) {
+    if (Nt < 1 || !At || !Mt) return fail(STFD_EINVAL, "time_decompose: bad arguments");
+    Decomp D;
+    int rc = decompose(Nt, At, Mt, D);
+    if (rc) return rc;
+    for (int k = 0; k < Nt; ++k) {
+        if (lam_re) lam_re[k] = D.lam[k].real();
+        if (lam_im) lam_im[k] = D.lam[k].imag();
+        if (sigma) sigma[k] = D.s[k];
+    }
+    for (size_t i = 0; i < (size_t)Nt * Nt; ++i) {
+        if (X_re) X_re[i] = D.X[i].real();
+        if (X_im) X_im[i] = D.X[i].imag();
+    }
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        fill_report(D, rep);
+    }
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, const double* Mt,
+                             const stfd_opts* opts, void* hip_stream, stfd_problem** out) {
+    if (!space || Nt < 1 || !At || !Mt || !out) return fail(STFD_EINVAL, "fd_setup: bad arguments");
+    *out = nullptr;
+    stfd_opts o;
+    stfd_opts_default(&o);
+    if (opts) o = *opts;
+    if ((o.precision != STFD_PREC_FP32 && o.precision != STFD_PREC_FP64) || !(o.rtol >= 0.0) || o.max_refine < 0 ||
+        o.max_refine >= STFD_MAX_HIST)
+        return fail(STFD_EINVAL, "fd_setup: bad options");
+    const auto t0 = std::chrono::steady_clock::now();
+    Decomp D;
+    int rc = decompose(Nt, At, Mt, D);
+    if (rc) return rc;
+
+    auto* p = new (std::nothrow) stfd_problem();
+    if (!p) return fail(STFD_ENOMEM, "fd_setup: out of memory");
+    p->space = space;
+    p->opts = o;
+    p->Nt = Nt;
+    p->Mx = space->Mx;
+    p->b = space->half_band;
+    p->bp = std::max(16, (p->b + 15) / 16 * 16);
+    p->npair = D.npair;
+    p->nreal = D.nreal;
+    p->nsys = D.npair + D.nreal;
+    fill_report(D, &p->rep);
+    p->rep.half_band = p->b;
+    const bool f32 = o.precision == STFD_PREC_FP32;
+    const size_t smem = f32 ? std::max(stfd::band_ldl_smem<float>(p->bp), stfd::sweep_smem<float>(p->bp))
+                            : std::max(stfd::band_ldl_smem<double>(p->bp), stfd::sweep_smem<double>(p->bp));
+    if (smem > 160 * 1024) {
+        delete p;
+        return fail(STFD_EINVAL, "fd_setup: half-bandwidth too large for the LDS-staged kernels in this precision");
+    }
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int n = Nt, ns = p->nsys;
+
+    // sys = [pairs (Im > 0) | real]; columns of X: pairs 0..np-1, conj np..2np-1, real 2np..
+    std::vector<int> sys(ns);
+    for (int q = 0; q < D.npair; ++q) sys[q] = q;
+    for (int q = 0; q < D.nreal; ++q) sys[D.npair + q] = 2 * D.npair + q;
+    p->lam_sys.resize(2 * ns);
+    for (int q = 0; q < ns; ++q) {
+        p->lam_sys[2 * q] = D.lam[sys[q]].real();
+        p->lam_sys[2 * q + 1] = D.lam[sys[q]].imag();
+    }
+    // W1 = A_t^-1 conj(U_t) Sigma^-1  (n x n complex) -> [Re | Im] (n x 2n)
+    std::vector<cd> W1((size_t)n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) W1[(size_t)i * n + j] = std::conj(D.U[(size_t)i * n + j]);
+    stfd::chol_forward(n, D.L, W1.data(), n);
+    stfd::chol_backward(n, D.L, W1.data(), n);
+    std::vector<double> W1h((size_t)n * 2 * n);
+    std::vector<float> W1f((size_t)n * 2 * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            const cd v = W1[(size_t)i * n + j] / D.s[j];
+            W1h[(size_t)i * 2 * n + j] = v.real();
+            W1h[(size_t)i * 2 * n + n + j] = v.imag();
+        }
+    for (size_t i = 0; i < W1h.size(); ++i) W1f[i] = (float)W1h[i];
+    // W2 = V_t^T[:, sys]: W2[j][q] = V[sys_q][j]  (V^T[j][c] = V[c][j])
+    std::vector<double> W2h((size_t)2 * n * 2 * ns);
+    for (int j = 0; j < n; ++j)
+        for (int q = 0; q < ns; ++q) {
+            const cd v = D.V[(size_t)sys[q] * n + j];
+            // rows j (real part of T1) and n + j (imaginary part of T1)
+            W2h[(size_t)j * 2 * ns + q] = v.real();
+            W2h[(size_t)j * 2 * ns + ns + q] = v.imag();
+            W2h[(size_t)(n + j) * 2 * ns + q] = -v.imag();
+            W2h[(size_t)(n + j) * 2 * ns + ns + q] = v.real();
+        }
+    // Xb: rows q (real part of Z) and ns + q (imaginary part): c_q x_q^T with
+    // c = 2 for pairs, 1 for real; Re(Z Xb) = Zr Xr - Zi Xi
+    std::vector<double> Xbh((size_t)2 * ns * n);
+    for (int q = 0; q < ns; ++q) {
+        const double cq = q < D.npair ? 2.0 : 1.0;
+        for (int k = 0; k < n; ++k) {
+            const cd x = D.X[(size_t)k * n + sys[q]];
+            Xbh[(size_t)q * n + k] = cq * x.real();
+            Xbh[(size_t)(ns + q) * n + k] = -cq * x.imag();
+        }
+    }
+    // Bres = [A_t^T; M_t^T]  (2n x n)
+    std::vector<double> Bres((size_t)2 * n * n);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+            Bres[(size_t)j * n + k] = At[(size_t)k * n + j];
+            Bres[(size_t)(n + j) * n + k] = Mt[(size_t)k * n + j];
+        }
+    std::vector<float> W2f(W2h.begin(), W2h.end()), Xbf(Xbh.begin(), Xbh.end());
+
+    const stfd_space* s = space;
+    int e = 0;
+    if ((e = upload(&p->d_rowptr, s->rowptr.data(), s->rowptr.size() * sizeof(int), st)) ||
+        (e = upload(&p->d_col, s->col.data(), s->col.size() * sizeof(int), st)) ||
+        (e = upload(&p->d_valM, s->valM.data(), s->valM.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_valA, s->valA.data(), s->valA.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_lam, p->lam_sys.data(), p->lam_sys.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_W1, W1h.data(), W1h.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_Bres, Bres.data(), Bres.size() * sizeof(double), st))) {
+        stfd_problem_free(p);
+        return e;
+    }
+    if (f32) {
+        if ((e = upload(&p->d_W1f, W1f.data(), W1f.size() * sizeof(float), st)) ||
+            (e = upload(&p->d_W2, W2f.data(), W2f.size() * sizeof(float), st)) ||
+            (e = upload(&p->d_Xb, Xbf.data(), Xbf.size() * sizeof(float), st))) {
+            stfd_problem_free(p);
+            return e;
+        }
+    } else {
+        if ((e = upload(&p->d_W2, W2h.data(), W2h.size() * sizeof(double), st)) ||
+            (e = upload(&p->d_Xb, Xbh.data(), Xbh.size() * sizeof(double), st))) {
+            stfd_problem_free(p);
+            return e;
+        }
+    }
+    {
+        int zero = 0;
+        if ((e = upload(&p->d_flag, &zero, sizeof(int), st))) {
+            stfd_problem_free(p);
+            return e;
+        }
+    }
+    // host sources of the async uploads go out of scope: wait for them
+    hipError_t he = hipStreamSynchronize(st);
+    if (he != hipSuccess) {
+        stfd_problem_free(p);
+        return hip_fail(he, "fd_setup: stream synchronize");
+    }
+    const size_t es = f32 ? 8 : 16;   // complex element size
+    p->rep.factor_bytes = (double)ns * p->Mx * (p->bp + 1) * es;
+    p->rep.setup_seconds =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* rep) {
+    if (!p || !rep) return fail(STFD_EINVAL, "setup_report: bad arguments");
+    *rep = p->rep;
+    return STFD_OK;
+}
+
+extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
+    if (!p) return fail(STFD_EINVAL, "fd_factor: null problem");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const bool f32 = is_fp32(p);
+    if (!p->d_LB) {
+        const size_t bytes = (size_t)p->nsys * p->Mx * (p->bp + 1) * (f32 ? 8 : 16);
+        hipError_t e = hipMalloc(&p->d_LB, bytes);
+        if (e != hipSuccess) {
+            p->d_LB = nullptr;
+            return fail(STFD_ENOMEM, std::string("band factor storage: ") + hipGetErrorString(e));
+        }
+    }
+    HIPCHK(hipMemsetAsync(p->d_flag, 0, sizeof(int), st), "fd_factor: clear flag");
+    if (f32) {
+        HIPCHK(stfd::launch_band_init<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col, p->d_valM,
+                                             p->d_valA, p->d_lam, st), "band init");
+        HIPCHK(stfd::launch_band_ldl<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st), "band LDL^T");
+    } else {
+        HIPCHK(stfd::launch_band_init<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col, p->d_valM,
+                                              p->d_valA, p->d_lam, st), "band init");
+        HIPCHK(stfd::launch_band_ldl<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st), "band LDL^T");
+    }
+    p->factored = true;
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+namespace {
+
+// one FD application: X (FP64 residual or load, Mx x Nt per RHS) -> U += alpha FD(X)
+int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t st) {
+    const bool f32 = is_fp32(p);
+    const int Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
+    stfd::GemmArgs g{};
+    // step 2a: T1 = X W1   (Mx x 2Nt)
+    g.A = X;
+    g.B = (f32 && !p->opts.fwd_fp64) ? static_cast<const void*>(p->d_W1f) : static_cast<const void*>(p->d_W1);
+    g.C = p->d_T1;
+    g.M = Mx; g.N = 2 * Nt; g.K = Nt;
+    g.lda = Mx; g.ldb = 2 * Nt; g.ldc = Mx;
+    g.strideA = (long long)Mx * Nt; g.strideC = (long long)Mx * 2 * Nt;
+    g.batch = nrhs;
+    stfd::GemmKind k1 = !f32 ? stfd::GEMM_D_D_STORE_D
+                             : (p->opts.fwd_fp64 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_F_STORE_F);
+    HIPCHK(stfd::launch_gemm(k1, g, st), "forward transform 1");
+    // step 2b: G = T1 W2   (Mx x 2nsys)
+    g = stfd::GemmArgs{};
+    g.A = p->d_T1; g.B = p->d_W2; g.C = p->d_G;
+    g.M = Mx; g.N = 2 * ns; g.K = 2 * Nt;
+    g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
+    g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * 2 * ns;
+    g.batch = nrhs;
+    HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_STORE_F : stfd::GEMM_D_D_STORE_D, g, st), "forward transform 2");
+    // step 3: spatial solves, in place in G
+    if (f32)
+        HIPCHK(stfd::launch_band_sweeps<float>(p->d_LB, Mx, p->bp, ns, nrhs, p->d_G, p->d_G, st), "band sweeps");
+    else
+        HIPCHK(stfd::launch_band_sweeps<double>(p->d_LB, Mx, p->bp, ns, nrhs, p->d_G, p->d_G, st), "band sweeps");
+    // step 4: U += Re(Z Xb)
+    g = stfd::GemmArgs{};
+    g.A = p->d_G; g.B = p->d_Xb; g.C = U;
+    g.M = Mx; g.N = Nt; g.K = 2 * ns;
+    g.lda = Mx; g.ldb = Nt; g.ldc = Mx;
+    g.strideA = (long long)Mx * 2 * ns; g.strideC = (long long)Mx * Nt;
+    g.batch = nrhs; g.alpha = 1.0;
+    HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_ADD_D : stfd::GEMM_D_D_ADD_D, g, st), "back transform");
+    return STFD_OK;
+}
+
+// R = F - K_h U and squared norms (device) for nrhs blocks
+int residual(stfd_problem* p, int nrhs, const double* F, const double* U, double* R, hipStream_t st) {
+    const int Mx = p->Mx, Nt = p->Nt;
+    HIPCHK(stfd::launch_spatial_apply(Mx, Nt, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA, U, p->d_P, st),
+           "spatial operator");
+    stfd::GemmArgs g{};
+    g.A = p->d_P; g.B = p->d_Bres; g.C = R; g.F = F; g.partial = p->d_part;
+    g.M = Mx; g.N = Nt; g.K = 2 * Nt;
+    g.lda = Mx; g.ldb = Nt; g.ldc = Mx;
+    g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * Nt; g.strideF = (long long)Mx * Nt;
+    g.batch = nrhs;
+    HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_RESID, g, st), "residual");
+    HIPCHK(stfd::launch_reduce_partials(p->d_part, stfd::gemm_resid_partials(Mx, Nt, 1), nrhs, p->d_norms, st),
+           "residual norms");
+    return STFD_OK;
+}
+
+}  // namespace
+
+extern "C" int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, const double* U_dev, double* R_dev,
+                                double* norms, void* hip_stream) {
+    if (!p || nrhs < 1 || !F_dev || !U_dev || !R_dev) return fail(STFD_EINVAL, "kh_residual: bad arguments");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int rc = ensure_work(p, nrhs);
+    if (rc) return rc;
+    rc = residual(p, nrhs, F_dev, U_dev, R_dev, st);
+    if (rc) return rc;
+    if (norms) {
+        HIPCHK(hipMemcpyAsync(norms, p->d_norms, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st), "norms copy");
+        HIPCHK(hipStreamSynchronize(st), "kh_residual: sync");
+    }
+    return STFD_OK;
+}
+
+extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, double* U_dev, stfd_solve_report* rep,
+                             void* hip_stream) {
+    if (!p || nrhs < 1 || !F_dev || !U_dev) return fail(STFD_EINVAL, "fd_solve: bad arguments");
+    if (!p->factored) return fail(STFD_ESTATE, "fd_solve: call stfd_fd_factor first");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int rc = ensure_work(p, nrhs);
+    if (rc) return rc;
+    stfd_solve_report r{};
+    r.nrhs = nrhs;
+    const size_t n = (size_t)p->Mx * p->Nt * nrhs;
+    HIPCHK(stfd::launch_fill_zero(U_dev, n, st), "zero U");
+    std::vector<double> norms(2 * nrhs);
+    int flag = 0;
+    const double* X = F_dev;
+    int status = STFD_ENOCONV;
+    for (int it = 0; it <= p->opts.max_refine; ++it) {
+        rc = fd_apply(p, nrhs, X, U_dev, st);
+        if (rc) return rc;
+        rc = residual(p, nrhs, F_dev, U_dev, p->d_R, st);
+        if (rc) return rc;
+        HIPCHK(hipMemcpyAsync(norms.data(), p->d_norms, 2 * nrhs * sizeof(double), hipMemcpyDeviceToHost, st),
+               "norms copy");
+        if (it == 0) HIPCHK(hipMemcpyAsync(&flag, p->d_flag, sizeof(int), hipMemcpyDeviceToHost, st), "flag copy");
+        HIPCHK(hipStreamSynchronize(st), "fd_solve: sync");
+        if (flag) return fail(STFD_ENUMERIC, "fd_solve: zero or non-finite pivot in a band factor");
+        double rel = 0.0;
+        bool finite = true;
+        for (int q = 0; q < nrhs; ++q) {
+            const double rr = norms[2 * q], ff = norms[2 * q + 1];
+            if (!std::isfinite(rr)) finite = false;
+            rel = std::max(rel, ff > 0 ? std::sqrt(rr / ff) : std::sqrt(rr));
+        }
+        r.rel_residual[it] = rel;
+        r.iterations = it + 1;
+        if (!finite) {
+            status = STFD_ENUMERIC;
+            break;
+        }
+        if (rel <= p->opts.rtol) {
+            status = STFD_OK;
+            r.converged = 1;
+            break;
+        }
+        X = p->d_R;
+    }
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = r;
+    if (status == STFD_ENUMERIC) return fail(STFD_ENUMERIC, "fd_solve: non-finite residual");
+    if (status == STFD_ENOCONV) return fail(STFD_ENOCONV, "fd_solve: rtol not reached within max_refine");
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" void stfd_problem_free(stfd_problem* p) {
+    if (!p) return;
+    free_work(p);
+    (void)hipFree(p->d_rowptr);
+    (void)hipFree(p->d_col);
+    (void)hipFree(p->d_valM);
+    (void)hipFree(p->d_valA);
+    (void)hipFree(p->d_lam);
+    (void)hipFree(p->d_W1);
+    (void)hipFree(p->d_W1f);
+    (void)hipFree(p->d_W2);
+    (void)hipFree(p->d_Xb);
+    (void)hipFree(p->d_Bres);
+    (void)hipFree(p->d_LB);
+    (void)hipFree(p->d_flag);
+    delete p;
+}

@@ -1,0 +1,257 @@
+"""Python binding of the stfd C library (argument marshalling only).
+
+Every computation happens in libstfd.so: host FP64 setup in C++, the hot path
+in HIP kernels for gfx950.  PyTorch is used only to hold device memory and to
+name the HIP stream; if the library is missing this module raises on import
+of any entry point, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstfd.so")
+
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5, -6
+PREC_FP64, PREC_FP32 = 0, 1
+MAX_HIST = 64
+
+EXPORTED = [
+    "stfd_opts_default", "stfd_last_error", "stfd_assemble_time", "stfd_space_create",
+    "stfd_space_free", "stfd_space_info", "stfd_space_csr_size", "stfd_space_export_csr",
+    "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_fd_setup",
+    "stfd_fd_setup_report", "stfd_fd_factor", "stfd_fd_solve", "stfd_kh_residual",
+    "stfd_problem_free",
+]
+
+
+class StfdError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"stfd error {code}: {msg}")
+        self.code = code
+
+
+class Opts(C.Structure):
+    _fields_ = [("precision", C.c_int), ("fwd_fp64", C.c_int), ("rtol", C.c_double),
+                ("max_refine", C.c_int)]
+
+
+class SetupReport(C.Structure):
+    _fields_ = [("min_re_lambda", C.c_double), ("max_abs_lambda", C.c_double),
+                ("sigma_min", C.c_double), ("sigma_max", C.c_double), ("kappa2", C.c_double),
+                ("eig_residual", C.c_double), ("n_real", C.c_int), ("n_pairs", C.c_int),
+                ("n_sys", C.c_int), ("half_band", C.c_int), ("setup_seconds", C.c_double),
+                ("factor_bytes", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class SolveReport(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("nrhs", C.c_int),
+                ("rel_residual", C.c_double * MAX_HIST), ("seconds", C.c_double)]
+
+    def as_dict(self):
+        return {"iterations": self.iterations, "converged": bool(self.converged), "nrhs": self.nrhs,
+                "rel_residual": list(self.rel_residual[: self.iterations]), "seconds": self.seconds}
+
+
+_LIB = None
+
+
+def lib():
+    """Load libstfd.so (built by paper_2008_01996_amd.build); raise if absent."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not found: build it with python -m paper_2008_01996_amd.build")
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int)
+        vp = C.c_void_p
+        L.stfd_last_error.restype = C.c_char_p
+        L.stfd_opts_default.argtypes = [C.POINTER(Opts)]
+        L.stfd_assemble_time.argtypes = [C.c_int, dp, dp, dp, dp]
+        L.stfd_space_create.argtypes = [C.c_int, dp, C.c_int, ip, ip, C.POINTER(vp)]
+        L.stfd_space_free.argtypes = [vp]
+        L.stfd_space_free.restype = None
+        L.stfd_space_info.argtypes = [vp, ip, ip, ip, C.POINTER(C.c_longlong)]
+        L.stfd_space_csr_size.argtypes = [vp, C.c_int, ip, ip, C.POINTER(C.c_longlong)]
+        L.stfd_space_export_csr.argtypes = [vp, C.c_int, ip, ip, dp]
+        L.stfd_project_f.argtypes = [vp, C.c_int, dp, C.c_int, C.c_int, ip, ip, ip, dp, dp, dp]
+        L.stfd_assemble_load.argtypes = [vp, C.c_int, dp, dp, dp]
+        L.stfd_time_decompose.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.POINTER(SetupReport)]
+        L.stfd_fd_setup.argtypes = [vp, C.c_int, dp, dp, C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.stfd_fd_setup_report.argtypes = [vp, C.POINTER(SetupReport)]
+        L.stfd_fd_factor.argtypes = [vp, vp]
+        L.stfd_fd_solve.argtypes = [vp, C.c_int, vp, vp, C.POINTER(SolveReport), vp]
+        L.stfd_kh_residual.argtypes = [vp, C.c_int, vp, vp, vp, dp, vp]
+        L.stfd_problem_free.argtypes = [vp]
+        L.stfd_problem_free.restype = None
+        _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc != OK:
+        raise StfdError(rc, lib().stfd_last_error().decode())
+    return rc
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def assemble_time(t):
+    """A_t, M_t, C_t (row = test index) on the time nodes t (Sec. 2)."""
+    t = _f64(t)
+    nt = len(t) - 1
+    A = np.empty((nt, nt))
+    M = np.empty((nt, nt))
+    Cm = np.empty((nt, nt))
+    _check(lib().stfd_assemble_time(nt, _dp(t), _dp(A), _dp(M), _dp(Cm)))
+    return A, M, Cm
+
+
+def time_decompose(At, Mt):
+    """Host steps 1a/1b: eigenvalues (ordered pairs | conjugates | real),
+    unit-norm eigenvectors X (columns), singular values of X, report."""
+    At = _f64(At)
+    Mt = _f64(Mt)
+    n = At.shape[0]
+    lr, li, s = np.empty(n), np.empty(n), np.empty(n)
+    Xr, Xi = np.empty((n, n)), np.empty((n, n))
+    rep = SetupReport()
+    _check(lib().stfd_time_decompose(n, _dp(At), _dp(Mt), _dp(lr), _dp(li), _dp(Xr), _dp(Xi), _dp(s),
+                                      C.byref(rep)))
+    return lr + 1j * li, Xr + 1j * Xi, s, rep.as_dict()
+
+
+class Space:
+    """P1 space on a triangulation (mesh with xy, tri, dof, box attributes)."""
+
+    def __init__(self, mesh):
+        xy = _f64(mesh.xy).reshape(-1)
+        tri = np.ascontiguousarray(mesh.tri, dtype=np.int32).reshape(-1)
+        dof = np.ascontiguousarray(mesh.dof, dtype=np.int32)
+        self._h = C.c_void_p()
+        self.box = np.asarray(mesh.box, dtype=np.float64)
+        _check(lib().stfd_space_create(len(dof), _dp(xy), len(tri) // 3, _ip(tri), _ip(dof), C.byref(self._h)))
+        mx, nt, hb = C.c_int(), C.c_int(), C.c_int()
+        nnz = C.c_longlong()
+        _check(lib().stfd_space_info(self._h, C.byref(mx), C.byref(nt), C.byref(hb), C.byref(nnz)))
+        self.Mx, self.ntri, self.half_band, self.nnz = mx.value, nt.value, hb.value, nnz.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.stfd_space_free(h)
+            self._h = None
+
+    def csr(self, which):
+        """(rowptr, col, val, shape) of M_x (0), A_x (1) or M10 (2)."""
+        r, c = C.c_int(), C.c_int()
+        nnz = C.c_longlong()
+        _check(lib().stfd_space_csr_size(self._h, which, C.byref(r), C.byref(c), C.byref(nnz)))
+        rp = np.empty(r.value + 1, np.int32)
+        cl = np.empty(nnz.value, np.int32)
+        vl = np.empty(nnz.value)
+        _check(lib().stfd_space_export_csr(self._h, which, _ip(rp), _ip(cl), _dp(vl)))
+        return rp, cl, vl, (r.value, c.value)
+
+    def project_f(self, t, modes, kind=0):
+        """Prism means F (ntri x Nt) of a separable f (kind 0: random modes,
+        kind 1: manufactured time profile 2t + 2 pi^2 t^2)."""
+        t = _f64(t)
+        nt = len(t) - 1
+        a = np.ascontiguousarray(modes.a, np.int32)
+        b = np.ascontiguousarray(modes.b, np.int32)
+        d = np.ascontiguousarray(modes.d, np.int32)
+        c = _f64(modes.c)
+        F = np.empty((nt, self.ntri))           # column-major ntri x Nt
+        _check(lib().stfd_project_f(self._h, nt, _dp(t), kind, len(a), _ip(a), _ip(b), _ip(d), _dp(c),
+                                    _dp(self.box), _dp(F)))
+        return F.T
+
+    def assemble_load(self, Ct, F):
+        """F~ = M10 F C_t^T as an (M_x, N_t) array."""
+        Ct = _f64(Ct)
+        nt = Ct.shape[0]
+        Fc = np.ascontiguousarray(np.asarray(F, dtype=np.float64).T)      # column-major
+        out = np.empty((nt, self.Mx))
+        _check(lib().stfd_assemble_load(self._h, nt, _dp(Ct), _dp(Fc), _dp(out)))
+        return out.T
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+class Problem:
+    """FD solver for one (space, time mesh) pair on the current GPU."""
+
+    def __init__(self, space: Space, At, Mt, precision="fp32", fwd_fp64=True, rtol=1e-10, max_refine=30,
+                 stream=None):
+        self.space = space        # keep alive: the problem refers to it
+        At = _f64(At)
+        Mt = _f64(Mt)
+        self.Nt = At.shape[0]
+        self.Mx = space.Mx
+        o = Opts()
+        _check(lib().stfd_opts_default(C.byref(o)))
+        o.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
+        o.fwd_fp64 = int(bool(fwd_fp64))
+        o.rtol = float(rtol)
+        o.max_refine = int(max_refine)
+        self.precision = precision
+        self._h = C.c_void_p()
+        _check(lib().stfd_fd_setup(space._h, self.Nt, _dp(At), _dp(Mt), C.byref(o),
+                                   C.c_void_p(_stream_ptr(stream)), C.byref(self._h)))
+        rep = SetupReport()
+        _check(lib().stfd_fd_setup_report(self._h, C.byref(rep)))
+        self.setup_report = rep.as_dict()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _LIB is not None:
+            _LIB.stfd_problem_free(h)
+            self._h = None
+
+    def factor(self, stream=None):
+        _check(lib().stfd_fd_factor(self._h, C.c_void_p(_stream_ptr(stream))))
+
+    def solve(self, F, U, stream=None, check=True):
+        """F, U: torch float64 CUDA tensors of shape (nrhs, N_t, M_x) (the
+        [rhs][k][i] layout).  Returns the solve report as a dict."""
+        assert F.dtype == U.dtype and F.is_contiguous() and U.is_contiguous()
+        assert F.shape == U.shape and F.shape[1:] == (self.Nt, self.Mx)
+        rep = SolveReport()
+        rc = lib().stfd_fd_solve(self._h, F.shape[0], C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
+                                 C.byref(rep), C.c_void_p(_stream_ptr(stream)))
+        out = rep.as_dict()
+        out["status"] = rc
+        if check:
+            _check(rc)
+        return out
+
+    def kh_residual(self, F, U, R, stream=None):
+        """R = F - K_h U on the device; returns (||R||^2, ||F||^2) per RHS."""
+        n = F.shape[0]
+        norms = np.empty(2 * n)
+        _check(lib().stfd_kh_residual(self._h, n, C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
+                                      C.c_void_p(R.data_ptr()), _dp(norms), C.c_void_p(_stream_ptr(stream))))
+        return norms.reshape(n, 2)

@@ -1,0 +1,190 @@
+"""GPU parity of the FD solve (through the C-ABI) against the FP64 oracle.
+
+Inputs come from the shared seeded generators; the oracle builds its own
+matrices and load from them and solves in FP64 (sparse LU of K_h on tiny
+meshes, Algorithm FD + refinement otherwise).  The GPU receives the same
+matrices (parity of the solver) or assembles everything itself (end to end).
+Tolerance: relative l2 error <= 1e-10 and relative residual <= 1e-10 for both
+precisions (the FP32 form is refined in FP64 to the same target).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import load
+from oracle import solvers as so
+from oracle import space_matrices as sm
+from oracle import time_matrices as tm
+
+torch = pytest.importorskip("torch")
+from paper_2008_01996_amd import stfd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+def _oracle_case(mesh, t, rhs, seeds=(3000,)):
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, M10 = sm.assemble(mesh)
+    Fs = []
+    for sd in seeds:
+        if rhs == "manufactured":
+            F = load.manufactured_cell_means(mesh, t)
+        else:
+            F = load.modes_cell_means(mesh, t, w.random_modes(sd))
+        Fs.append(load.assemble_load(M10, F, Ct))
+    return At, Mt, Mx, Ax, Fs
+
+
+def _oracle_solution(At, Mt, Mx, Ax, F):
+    if Mx.shape[0] * At.shape[0] <= 40000:
+        return so.direct(At, Mt, Mx, Ax, F)
+    U, _ = so.refine(At, Mt, Mx, Ax, F, max_iter=6)
+    return U
+
+
+def _to_dev(Fs):
+    arr = np.stack([F.T for F in Fs])            # (nrhs, Nt, Mx) = [rhs][k][i]
+    return torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
+
+
+def _gpu_solve(space, At, Mt, Fs, precision, fwd_fp64=True, max_refine=30):
+    prob = stfd.Problem(space, At, Mt, precision=precision, fwd_fp64=fwd_fp64, max_refine=max_refine)
+    prob.factor()
+    F = _to_dev(Fs)
+    U = torch.empty_like(F)
+    rep = prob.solve(F, U)
+    torch.cuda.synchronize()
+    Us = [u.T.copy() for u in U.cpu().numpy()]
+    return Us, rep, prob
+
+
+def _check(At, Mt, Mx, Ax, Fs, Us, rep, tol=RTOL):
+    assert rep["converged"], rep
+    for F, U in zip(Fs, Us):
+        Uo = _oracle_solution(At, Mt, Mx, Ax, F)
+        err = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
+        res = so.rel_residual(At, Mt, Mx, Ax, F, U)
+        print(f"  rel err vs oracle {err:.2e}  rel residual (oracle K_h) {res:.2e}  iters {rep['iterations']}")
+        assert res <= tol
+        assert err <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_small_unit_square_manufactured(precision):
+    """h = 1/16, uniform N_t = 16 (3600 space-time DOFs), manufactured load."""
+    mesh = w.square_mesh(16)
+    t = w.uniform_times(16)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "manufactured")
+    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, precision)
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nc,t,nrhs", [
+    (9, w.graded_times(7), 3),          # M_x = 64, b = 9 (padded to 16), odd N_t -> a real eigenvalue
+    (12, w.paper_times(2), 1),          # M_x = 121 (ragged last panel), nonuniform paper mesh
+    (6, w.uniform_times(10, T=0.5), 17),  # two right-hand-side groups, the second ragged
+], ids=["graded7_rhs3", "paper2_rhs1", "uniform10_rhs17"])
+def test_ragged_shapes(precision, nc, t, nrhs):
+    mesh = w.square_mesh(nc)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[4000 + r for r in range(nrhs)])
+    Us, rep, prob = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, precision)
+    if len(t) - 1 == 7:
+        assert prob.setup_report["n_real"] >= 1
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_lshape_variable_rows(precision):
+    """L-shape (rows of 7 and 15 interior nodes), paper time mesh level 2."""
+    mesh = w.lshape_mesh(16)
+    t = w.paper_times(2)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[5000, 5001])
+    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, precision)
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+def test_end_to_end_library_assembly():
+    """The library assembles time matrices, spatial matrices and the load
+    itself; the result matches the all-oracle solution."""
+    mesh = w.square_mesh(16)
+    t = w.uniform_times(16)
+    sp = stfd.Space(mesh)
+    A, M, C = stfd.assemble_time(t)
+    Fl = sp.assemble_load(C, sp.project_f(t, w.manufactured_modes(), kind=1))
+    Us, rep, _ = _gpu_solve(sp, A, M, [Fl], "fp32")
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "manufactured")
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+def test_device_residual_is_kronecker_identity():
+    """R = F - K_h U on the device equals F - (M_x U A_t^T + A_x U M_t^T)."""
+    mesh = w.square_mesh(10)
+    t = w.paper_times(2)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[7, 8])
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision="fp64")
+    rng = np.random.default_rng(1)
+    Uh = [rng.standard_normal(F.shape) for F in Fs]
+    F = _to_dev(Fs)
+    U = _to_dev(Uh)
+    R = torch.empty_like(F)
+    norms = prob.kh_residual(F, U, R)
+    Rh = [r.T for r in R.cpu().numpy()]
+    for q in range(2):
+        Ro = so.residual(At, Mt, Mx, Ax, Fs[q], Uh[q])
+        assert np.abs(Rh[q] - Ro).max() <= 1e-13 * np.abs(Ro).max()
+        assert abs(norms[q, 0] - (Ro ** 2).sum()) <= 1e-12 * (Ro ** 2).sum()
+        assert abs(norms[q, 1] - (Fs[q] ** 2).sum()) <= 1e-12 * (Fs[q] ** 2).sum()
+
+
+def test_fp32_forward_variant_still_converges():
+    """With the first forward GEMM in FP32 the refinement still reaches 1e-10
+    (more iterations: that GEMM amplifies FP32 rounding by kappa_2(X_t))."""
+    mesh = w.square_mesh(12)
+    t = w.uniform_times(32)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random")
+    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, "fp32", fwd_fp64=False, max_refine=40)
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+def test_solve_is_deterministic():
+    mesh = w.square_mesh(16)
+    t = w.uniform_times(16)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[1, 2])
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision="fp32")
+    prob.factor()
+    F = _to_dev(Fs)
+    U1 = torch.empty_like(F)
+    U2 = torch.empty_like(F)
+    prob.solve(F, U1)
+    prob.factor()
+    prob.solve(F, U2)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
+
+
+def test_nonconvergence_is_reported():
+    """max_refine = 0 with an unreachable target returns ENOCONV (host-forced)."""
+    mesh = w.square_mesh(8)
+    t = w.uniform_times(64)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random")
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision="fp32", rtol=1e-16, max_refine=0)
+    prob.factor()
+    F = _to_dev(Fs)
+    U = torch.empty_like(F)
+    rep = prob.solve(F, U, check=False)
+    assert rep["status"] == stfd.ENOCONV and rep["iterations"] == 1
+
+
+def test_solve_before_factor():
+    mesh = w.square_mesh(4)
+    At, Mt, _, _, Fs = _oracle_case(mesh, w.uniform_times(4), "random")
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt)
+    F = _to_dev(Fs)
+    with pytest.raises(stfd.StfdError) as e:
+        prob.solve(F, torch.empty_like(F))
+    assert e.value.code == stfd.ESTATE

@@ -1,0 +1,161 @@
+"""CPU tests of the C library: it loads, exports the declared C-ABI, and its
+host-side steps (time/space assembly, load, eigendecomposition, errors) agree
+with the oracle.  No GPU call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+import scipy.sparse as sps
+
+import workloads as w
+from oracle import load
+from oracle import solvers as so
+from oracle import space_matrices as sm
+from oracle import time_matrices as tm
+from paper_2008_01996_amd import stfd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(stfd_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = stfd.lib()
+    declared = _declared_symbols()
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(stfd.EXPORTED) <= declared
+
+
+@pytest.mark.parametrize("t", [w.paper_times(0), w.paper_times(4), w.uniform_times(48, T=2.0),
+                               w.graded_times(96), np.array([0.0, 0.3])],
+                         ids=["paper0", "paper4", "uniform48", "graded96", "single"])
+def test_assemble_time_matches_oracle(t):
+    A, M, C = stfd.assemble_time(t)
+    Ao, Mo, Co = tm.kernel(t)
+    for X, Y in ((A, Ao), (M, Mo), (C, Co)):
+        assert np.abs(X - Y).max() <= 1e-13 * np.abs(Y).max()
+
+
+@pytest.mark.parametrize("mesh", [w.square_mesh(7), w.lshape_mesh(8)], ids=["square7", "lshape8"])
+def test_space_matrices_match_oracle(mesh):
+    sp = stfd.Space(mesh)
+    refs = sm.assemble(mesh)
+    for which, ref in enumerate(refs):
+        rp, cl, vl, shape = sp.csr(which)
+        P = sps.csr_matrix((vl, cl, rp), shape=shape)
+        assert P.shape == ref.shape
+        assert abs(P - ref).max() <= 1e-15 * abs(ref).max()
+    coo = refs[0].tocoo()
+    assert sp.half_band == int(np.abs(coo.row - coo.col).max())
+    assert sp.Mx == mesh.n_dof
+
+
+def test_square_mesh_band_is_row_length_plus_one():
+    sp = stfd.Space(w.square_mesh(16))
+    assert sp.half_band == 16        # 15 interior nodes per row, SW-NE diagonal
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_load_matches_oracle(kind):
+    mesh = w.square_mesh(6)
+    t = w.paper_times(1)
+    sp = stfd.Space(mesh)
+    _, _, Ct = tm.kernel(t)
+    _, _, M10 = sm.assemble(mesh)
+    if kind == 0:
+        modes = w.random_modes(4001)
+        Fo = load.modes_cell_means(mesh, t, modes)
+    else:
+        modes = w.manufactured_modes()
+        Fo = load.manufactured_cell_means(mesh, t)
+    F = sp.project_f(t, modes, kind)
+    assert np.abs(F - Fo).max() <= 1e-13 * np.abs(Fo).max()
+    Ft = sp.assemble_load(Ct, F)
+    Fto = load.assemble_load(M10, Fo, Ct)
+    assert np.abs(Ft - Fto).max() <= 1e-13 * np.abs(Fto).max()
+
+
+def _match(a, b):
+    """max distance of a matching of two eigenvalue lists (greedy nearest)."""
+    b = list(b)
+    worst = 0.0
+    for z in a:
+        j = int(np.argmin([abs(z - y) for y in b]))
+        worst = max(worst, abs(z - b[j]))
+        b.pop(j)
+    return worst
+
+
+@pytest.mark.parametrize("t", [w.paper_times(0), w.uniform_times(16), w.paper_times(4), w.graded_times(64)],
+                         ids=["paper0", "uniform16", "paper4", "graded64"])
+def test_time_decompose_matches_oracle(t):
+    A, M, _ = tm.kernel(t)
+    lam, X, s, rep = stfd.time_decompose(A, M)
+    lo = sl.eigvals(M, A)
+    # Bauer-Fike: both eigensolvers are backward stable, so each eigenvalue
+    # moves by at most ~ kappa_2(X) times a rounding-size perturbation
+    assert _match(lam, lo) <= 50 * np.finfo(float).eps * rep["kappa2"] * np.abs(lo).max()
+    # M X = A X diag(lambda), unit columns, exact conjugate pairs first
+    assert np.abs(M @ X - (A @ X) * lam).max() <= 1e-13 * np.abs(lam).max()
+    assert np.allclose(np.linalg.norm(X, axis=0), 1.0, atol=1e-14)
+    npair, nreal = rep["n_pairs"], rep["n_real"]
+    assert 2 * npair + nreal == len(lam)
+    assert np.array_equal(lam[npair:2 * npair], lam[:npair].conj())
+    assert np.array_equal(X[:, npair:2 * npair], X[:, :npair].conj())
+    assert np.all(lam[:npair].imag > 0) and np.all(lam[2 * npair:].imag == 0)
+    # singular values of X agree with LAPACK on the same (phase-invariant) normalisation
+    dec = so.decompose(A, M, normalization="unit")
+    assert abs(rep["kappa2"] / dec.kappa - 1) < 1e-6
+    assert np.abs(s - np.linalg.svd(X, compute_uv=False)).max() <= 1e-12 * s.max()
+    assert rep["min_re_lambda"] > 0 and rep["eig_residual"] < 1e-13
+
+
+def test_error_paths():
+    t = w.uniform_times(4)
+    A, M, _ = tm.kernel(t)
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.assemble_time(np.array([0.0, 0.5, 0.5, 1.0]))
+    assert e.value.code == stfd.EINVAL
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.time_decompose(-A, M)                   # not SPD
+    assert e.value.code == stfd.ENUMERIC
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.time_decompose(A, -M)                   # Re(lambda) < 0
+    assert e.value.code == stfd.ENUMERIC
+    Mn = M.copy()
+    Mn[1, 2] = np.nan
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.time_decompose(A, Mn)
+    assert e.value.code == stfd.ENUMERIC
+    mesh = w.square_mesh(3)
+    bad = w.Mesh(xy=mesh.xy, tri=mesh.tri[:, ::-1].copy(), dof=mesh.dof, h=mesh.h, rows=mesh.rows, box=mesh.box)
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.Space(bad)                              # clockwise triangles
+    assert e.value.code == stfd.EINVAL
+    dup = mesh.dof.copy()
+    dup[dup == 1] = 0
+    bad = w.Mesh(xy=mesh.xy, tri=mesh.tri, dof=dup, h=mesh.h, rows=mesh.rows, box=mesh.box)
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.Space(bad)                              # repeated interior number
+    assert e.value.code == stfd.EINVAL
+    assert stfd.lib().stfd_opts_default(None) == stfd.EINVAL
+
+
+def test_solve_before_factor_is_a_state_error():
+    """Needs no GPU: the order check happens before any device call."""
+    lib = stfd.lib()
+    rep = stfd.SolveReport()
+    rc = lib.stfd_fd_solve(None, 1, None, None, ctypes.byref(rep), None)
+    assert rc == stfd.EINVAL
