@@ -216,6 +216,24 @@ int stfd_fd_factor(stfd_problem* p, void* hip_stream);
 int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, double* U_dev,
                   stfd_solve_report* rep, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Single stages, for tests and for callers that drive their own iteration.
+ *
+ * stfd_fd_apply: one application of Algorithm FD without refinement,
+ *   U_dev = FD(X_dev), X_dev and U_dev device FP64 [rhs][k][i] blocks
+ *   (steps 2-4 of Sec. 4.4 with the precision of the options).
+ * stfd_spatial_solve: step 3 alone.  G_dev/Z_dev hold, per RHS, the
+ *   column-major M_x x 2 n_sys real matrix [Re g_0 .. Re g_{n-1} | Im g_0 ..
+ *   Im g_{n-1}] in the working precision (float for STFD_PREC_FP32, double
+ *   otherwise); system k solves (M_x + lambda_k A_x) z_k = g_k with lambda_k
+ *   the k-th system eigenvalue (pairs with Im > 0 first, then real ones).
+ *   Z_dev may equal G_dev.  Both need stfd_fd_factor first (STFD_ESTATE).
+ * stfd_system_lambdas: the n_sys eigenvalues (host, 2 n_sys doubles re/im).
+ * ------------------------------------------------------------------------- */
+int stfd_fd_apply(stfd_problem* p, int nrhs, const double* X_dev, double* U_dev, void* hip_stream);
+int stfd_spatial_solve(stfd_problem* p, int nrhs, const void* G_dev, void* Z_dev, void* hip_stream);
+int stfd_system_lambdas(const stfd_problem* p, double* lam);
+
 /* K_h applied on the device: R_dev = F_dev - K_h U_dev for nrhs blocks, and
  * the squared 2-norms of every R and F block in norms[2*nrhs] (host, may be
  * NULL; when given the call synchronises hip_stream).  Used by the solve and

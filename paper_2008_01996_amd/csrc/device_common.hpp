@@ -4,7 +4,10 @@
 // MFMA 16x16x4 operand layout (wave of 64 lanes, one 16x16 output block):
 //   A operand: lane l holds A[m = l % 16][k = l / 16]
 //   B operand: lane l holds B[k = l / 16][n = l % 16]
-//   D output : lane l holds D[m = 4 * (l / 16) + j][n = l % 16], j = 0..3
+//   D output : lane l, register j holds D[m][n = l % 16] with
+//              m = 4 * (l / 16) + j   for the FP32 instruction,
+//              m = (l / 16) + 4 * j   for the FP64 instruction
+//   (mfma_row<T> below; both measured on gfx950).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -53,6 +56,14 @@ template <>
 __device__ __forceinline__ vec4<double>::type mfma16x16x4<double>(double a, double b, vec4<double>::type c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+
+// output row m of register j in lane group g = l / 16
+template <typename T>
+__device__ __forceinline__ int mfma_row(int g, int j);
+template <>
+__device__ __forceinline__ int mfma_row<float>(int g, int j) { return 4 * g + j; }
+template <>
+__device__ __forceinline__ int mfma_row<double>(int g, int j) { return g + 4 * j; }
 
 template <typename T>
 __device__ __forceinline__ typename vec4<T>::type zero4() {

@@ -163,11 +163,11 @@ __global__ void __launch_bounds__(256) band_ldl_kernel(cplx<T>* __restrict__ LB,
                 accI = mfma16x16x4<T>(ar, bi, accI);
                 accI = mfma16x16x4<T>(ai, br, accI);
             }
-            // D[c' = c0 + 4 lk + j][r = r0 + li]
+            // D[c' = c0 + mfma_row(lk, j)][r = r0 + li]
             const int r = r0 + li;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int c = c0 + 4 * lk + j;
+                const int c = c0 + mfma_row<T>(lk, j);
                 const int d = r - c;
                 if (r < Mx && c < Mx && d >= 0 && d <= bp) {
                     cplx<T>* p = base + (size_t)c * bp1 + d;

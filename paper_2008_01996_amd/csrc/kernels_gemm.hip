@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         __syncthreads();
     }
 
-    // epilogue: acc[tn][tm][j] = C[m = m0 + wm + 16 tm + li][n = n0 + wn + 16 tn + 4 lk + j]
+    // epilogue: acc[tn][tm][j] = C[m = m0 + wm + 16 tm + li][n = n0 + wn + 16 tn + mfma_row(lk, j)]
     double s_r = 0.0, s_f = 0.0;
 #pragma unroll
     for (int tn = 0; tn < 2; ++tn)
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = m0 + wm + 16 * tm + li;
-                const int n = n0 + wn + 16 * tn + 4 * lk + j;
+                const int n = n0 + wn + 16 * tn + mfma_row<TC>(lk, j);
                 if (m >= g.M || n >= g.N) continue;
                 const size_t off = (size_t)batch * g.strideC + (size_t)m + (size_t)n * g.ldc;
                 const TC v = acc[tn][tm][j];

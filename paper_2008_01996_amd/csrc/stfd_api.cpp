@@ -510,6 +510,37 @@ extern "C" int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, 
     return STFD_OK;
 }
 
+extern "C" int stfd_fd_apply(stfd_problem* p, int nrhs, const double* X_dev, double* U_dev, void* hip_stream) {
+    if (!p || nrhs < 1 || !X_dev || !U_dev) return fail(STFD_EINVAL, "fd_apply: bad arguments");
+    if (!p->factored) return fail(STFD_ESTATE, "fd_apply: call stfd_fd_factor first");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    int rc = ensure_work(p, nrhs);
+    if (rc) return rc;
+    HIPCHK(stfd::launch_fill_zero(U_dev, (size_t)p->Mx * p->Nt * nrhs, st), "zero U");
+    rc = fd_apply(p, nrhs, X_dev, U_dev, st);
+    if (rc) return rc;
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" int stfd_spatial_solve(stfd_problem* p, int nrhs, const void* G_dev, void* Z_dev, void* hip_stream) {
+    if (!p || nrhs < 1 || !G_dev || !Z_dev) return fail(STFD_EINVAL, "spatial_solve: bad arguments");
+    if (!p->factored) return fail(STFD_ESTATE, "spatial_solve: call stfd_fd_factor first");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    if (is_fp32(p))
+        HIPCHK(stfd::launch_band_sweeps<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G_dev, Z_dev, st), "sweeps");
+    else
+        HIPCHK(stfd::launch_band_sweeps<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G_dev, Z_dev, st), "sweeps");
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" int stfd_system_lambdas(const stfd_problem* p, double* lam) {
+    if (!p || !lam) return fail(STFD_EINVAL, "system_lambdas: bad arguments");
+    std::copy(p->lam_sys.begin(), p->lam_sys.end(), lam);
+    return STFD_OK;
+}
+
 extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, double* U_dev, stfd_solve_report* rep,
                              void* hip_stream) {
     if (!p || nrhs < 1 || !F_dev || !U_dev) return fail(STFD_EINVAL, "fd_solve: bad arguments");

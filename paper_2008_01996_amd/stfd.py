@@ -24,7 +24,7 @@ EXPORTED = [
     "stfd_space_free", "stfd_space_info", "stfd_space_csr_size", "stfd_space_export_csr",
     "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_fd_setup",
     "stfd_fd_setup_report", "stfd_fd_factor", "stfd_fd_solve", "stfd_kh_residual",
-    "stfd_problem_free",
+    "stfd_problem_free", "stfd_fd_apply", "stfd_spatial_solve", "stfd_system_lambdas",
 ]
 
 
@@ -89,6 +89,9 @@ def lib():
         L.stfd_fd_factor.argtypes = [vp, vp]
         L.stfd_fd_solve.argtypes = [vp, C.c_int, vp, vp, C.POINTER(SolveReport), vp]
         L.stfd_kh_residual.argtypes = [vp, C.c_int, vp, vp, vp, dp, vp]
+        L.stfd_fd_apply.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.stfd_spatial_solve.argtypes = [vp, C.c_int, vp, vp, vp]
+        L.stfd_system_lambdas.argtypes = [vp, dp]
         L.stfd_problem_free.argtypes = [vp]
         L.stfd_problem_free.restype = None
         _LIB = L
@@ -247,6 +250,24 @@ class Problem:
         if check:
             _check(rc)
         return out
+
+    def apply(self, X, U, stream=None):
+        """One FD application without refinement: U = FD(X) (device tensors
+        (nrhs, N_t, M_x) float64)."""
+        _check(lib().stfd_fd_apply(self._h, X.shape[0], C.c_void_p(X.data_ptr()), C.c_void_p(U.data_ptr()),
+                                   C.c_void_p(_stream_ptr(stream))))
+
+    def spatial_solve(self, G, Z, stream=None):
+        """Step 3 alone on device tensors of shape (nrhs, 2 n_sys, M_x) in the
+        working precision (float32 for fp32, float64 for fp64)."""
+        _check(lib().stfd_spatial_solve(self._h, G.shape[0], C.c_void_p(G.data_ptr()), C.c_void_p(Z.data_ptr()),
+                                        C.c_void_p(_stream_ptr(stream))))
+
+    def system_lambdas(self):
+        n = self.setup_report["n_sys"]
+        lam = np.empty(2 * n)
+        _check(lib().stfd_system_lambdas(self._h, _dp(lam)))
+        return lam[0::2] + 1j * lam[1::2]
 
     def kh_residual(self, F, U, R, stream=None):
         """R = F - K_h U on the device; returns (||R||^2, ||F||^2) per RHS."""

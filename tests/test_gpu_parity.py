@@ -5,7 +5,10 @@ matrices and load from them and solves in FP64 (sparse LU of K_h on tiny
 meshes, Algorithm FD + refinement otherwise).  The GPU receives the same
 matrices (parity of the solver) or assembles everything itself (end to end).
 Tolerance: relative l2 error <= 1e-10 and relative residual <= 1e-10 for both
-precisions (the FP32 form is refined in FP64 to the same target).
+precisions (the FP32 form is refined in FP64 to the same target).  The error
+is the residual times a problem-dependent amplification of order one to ten,
+so these solves refine to a residual of 1e-11 to make the 1e-10 agreement
+hold; the benchmark solves to the metric's 1e-10 and reports its error.
 """
 import math
 
@@ -24,6 +27,7 @@ from paper_2008_01996_amd import stfd  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-10
+SOLVE_RTOL = 1e-11
 
 
 def _oracle_case(mesh, t, rhs, seeds=(3000,)):
@@ -51,8 +55,8 @@ def _to_dev(Fs):
     return torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
 
 
-def _gpu_solve(space, At, Mt, Fs, precision, fwd_fp64=True, max_refine=30):
-    prob = stfd.Problem(space, At, Mt, precision=precision, fwd_fp64=fwd_fp64, max_refine=max_refine)
+def _gpu_solve(space, At, Mt, Fs, precision, fwd_fp64=True, max_refine=30, rtol=SOLVE_RTOL):
+    prob = stfd.Problem(space, At, Mt, precision=precision, fwd_fp64=fwd_fp64, max_refine=max_refine, rtol=rtol)
     prob.factor()
     F = _to_dev(Fs)
     U = torch.empty_like(F)
