@@ -241,6 +241,32 @@ int stfd_system_lambdas(const stfd_problem* p, double* lam);
 int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, const double* U_dev,
                      double* R_dev, double* norms, void* hip_stream);
 
+/* ---------------------------------------------------------------------------
+ * Per-stage device timing with HIP events recorded on the caller's stream
+ * around every kernel launch (the survey of where time goes; off by default).
+ * Stages: STFD_ST_BAND_INIT, STFD_ST_BAND_LDL (factor), STFD_ST_FWD1,
+ * STFD_ST_FWD2 (forward transforms), STFD_ST_SWEEP_FWD, STFD_ST_SWEEP_BWD,
+ * STFD_ST_BACK (back transform and update), STFD_ST_SPATIAL, STFD_ST_RESID,
+ * STFD_ST_REDUCE (FP64 residual).
+ * stfd_profile(p, 1) enables and clears the accumulators, (p, 0) disables.
+ * stfd_profile_read waits for the recorded events and returns, per stage, the
+ * summed milliseconds and the number of launches since the last clear
+ * (ms, counts: STFD_NSTAGE entries each, caller-owned).
+ * ------------------------------------------------------------------------- */
+#define STFD_NSTAGE 10
+#define STFD_ST_BAND_INIT 0
+#define STFD_ST_BAND_LDL 1
+#define STFD_ST_FWD1 2
+#define STFD_ST_FWD2 3
+#define STFD_ST_SWEEP_FWD 4
+#define STFD_ST_SWEEP_BWD 5
+#define STFD_ST_BACK 6
+#define STFD_ST_SPATIAL 7
+#define STFD_ST_RESID 8
+#define STFD_ST_REDUCE 9
+int stfd_profile(stfd_problem* p, int enable);
+int stfd_profile_read(stfd_problem* p, double* ms, long long* counts);
+
 void stfd_problem_free(stfd_problem* p);
 
 #ifdef __cplusplus

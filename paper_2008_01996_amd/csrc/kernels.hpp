@@ -51,8 +51,10 @@ hipError_t launch_band_init(void* LB, int Mx, int bp, int nsys, const int* rowpt
 template <typename T>
 hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStream_t st);
 template <typename T>
-hipError_t launch_band_sweeps(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                              hipStream_t st);
+hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
+                               hipStream_t st);
+template <typename T>
+hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st);
 template <typename T>
 size_t band_ldl_smem(int bp);
 template <typename T>

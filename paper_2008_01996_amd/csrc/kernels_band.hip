@@ -432,20 +432,25 @@ size_t sweep_smem(int bp) {
 }
 
 template <typename T>
-hipError_t launch_band_sweeps(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                              hipStream_t st) {
+hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
+                               hipStream_t st) {
     const size_t smem = sweep_smem<T>(bp);
     hipError_t e = hipFuncSetAttribute((const void*)band_forward_kernel<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute((const void*)band_backward_kernel<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)smem);
-    if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + 15) / 16);
     hipLaunchKernelGGL(band_forward_kernel<T>, grid, dim3(256), smem, st, static_cast<const cplx<T>*>(LB), Mx,
                        bp, nsys, nrhs, static_cast<const T*>(G), static_cast<T*>(W));
-    e = hipGetLastError();
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
+    const size_t smem = sweep_smem<T>(bp);
+    hipError_t e = hipFuncSetAttribute((const void*)band_backward_kernel<T>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
+    dim3 grid(nsys, (nrhs + 15) / 16);
     hipLaunchKernelGGL(band_backward_kernel<T>, grid, dim3(256), smem, st, static_cast<const cplx<T>*>(LB), Mx,
                        bp, nsys, nrhs, static_cast<T*>(W));
     return hipGetLastError();
@@ -457,8 +462,10 @@ template hipError_t launch_band_init<double>(void*, int, int, int, const int*, c
                                              const double*, const double*, hipStream_t);
 template hipError_t launch_band_ldl<float>(void*, int, int, int, int*, hipStream_t);
 template hipError_t launch_band_ldl<double>(void*, int, int, int, int*, hipStream_t);
-template hipError_t launch_band_sweeps<float>(const void*, int, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_band_sweeps<double>(const void*, int, int, int, int, const void*, void*, hipStream_t);
+template hipError_t launch_band_forward<float>(const void*, int, int, int, int, const void*, void*, hipStream_t);
+template hipError_t launch_band_forward<double>(const void*, int, int, int, int, const void*, void*, hipStream_t);
+template hipError_t launch_band_backward<float>(const void*, int, int, int, int, void*, hipStream_t);
+template hipError_t launch_band_backward<double>(const void*, int, int, int, int, void*, hipStream_t);
 template size_t band_ldl_smem<float>(int);
 template size_t band_ldl_smem<double>(int);
 template size_t sweep_smem<float>(int);

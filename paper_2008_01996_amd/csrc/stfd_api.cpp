@@ -45,6 +45,17 @@ struct stfd_problem {
     double* d_R = nullptr;      // Mx x Nt per RHS
     double* d_part = nullptr;
     double* d_norms = nullptr;
+    // per-stage event timing
+    struct ProfRec {
+        int stage;
+        hipEvent_t a, b;
+    };
+    bool prof_on = false;
+    std::vector<hipEvent_t> ev_pool;    // all events ever created
+    size_t ev_used = 0;                 // events handed out since the last drain
+    std::vector<ProfRec> prof_recs;
+    double prof_ms[STFD_NSTAGE] = {};
+    long long prof_cnt[STFD_NSTAGE] = {};
 };
 
 namespace {
@@ -83,6 +94,48 @@ void free_work(stfd_problem* p) {
     p->d_P = p->d_R = p->d_part = p->d_norms = nullptr;
     p->nrhs_cap = 0;
 }
+
+hipEvent_t next_event(stfd_problem* p) {
+    if (p->ev_used == p->ev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        p->ev_pool.push_back(e);
+    }
+    return p->ev_pool[p->ev_used++];
+}
+
+// waits for the recorded events, adds their durations to the accumulators and
+// recycles them
+int drain_profile(stfd_problem* p) {
+    for (auto& r : p->prof_recs) {
+        HIPCHK(hipEventSynchronize(r.b), "profile: event synchronize");
+        float ms = 0.0f;
+        HIPCHK(hipEventElapsedTime(&ms, r.a, r.b), "profile: elapsed time");
+        p->prof_ms[r.stage] += ms;
+        p->prof_cnt[r.stage] += 1;
+    }
+    p->prof_recs.clear();
+    p->ev_used = 0;
+    return STFD_OK;
+}
+
+// brackets one kernel launch with events when profiling is on
+struct StageTimer {
+    stfd_problem* p;
+    int stage;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    StageTimer(stfd_problem* p_, int stage_, hipStream_t st_) : p(p_), stage(stage_), st(st_) {
+        if (p->prof_on && (a = next_event(p)) != nullptr) (void)hipEventRecord(a, st);
+    }
+    ~StageTimer() {
+        if (!a) return;
+        hipEvent_t b = next_event(p);
+        if (!b) return;
+        (void)hipEventRecord(b, st);
+        p->prof_recs.push_back({stage, a, b});
+    }
+};
 
 struct Decomp {
     int n = 0, npair = 0, nreal = 0;
@@ -420,14 +473,19 @@ extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
         }
     }
     HIPCHK(hipMemsetAsync(p->d_flag, 0, sizeof(int), st), "fd_factor: clear flag");
-    if (f32) {
-        HIPCHK(stfd::launch_band_init<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col, p->d_valM,
-                                             p->d_valA, p->d_lam, st), "band init");
-        HIPCHK(stfd::launch_band_ldl<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st), "band LDL^T");
-    } else {
-        HIPCHK(stfd::launch_band_init<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col, p->d_valM,
-                                              p->d_valA, p->d_lam, st), "band init");
-        HIPCHK(stfd::launch_band_ldl<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st), "band LDL^T");
+    {
+        StageTimer tm(p, STFD_ST_BAND_INIT, st);
+        HIPCHK(f32 ? stfd::launch_band_init<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col,
+                                                   p->d_valM, p->d_valA, p->d_lam, st)
+                   : stfd::launch_band_init<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col,
+                                                    p->d_valM, p->d_valA, p->d_lam, st),
+               "band init");
+    }
+    {
+        StageTimer tm(p, STFD_ST_BAND_LDL, st);
+        HIPCHK(f32 ? stfd::launch_band_ldl<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st)
+                   : stfd::launch_band_ldl<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st),
+               "band LDL^T");
     }
     p->factored = true;
     stfd::clear_error();
@@ -435,6 +493,23 @@ extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
 }
 
 namespace {
+
+int spatial_sweeps(stfd_problem* p, int nrhs, const void* G, void* Z, hipStream_t st) {
+    const bool f32 = is_fp32(p);
+    {
+        StageTimer tm(p, STFD_ST_SWEEP_FWD, st);
+        HIPCHK(f32 ? stfd::launch_band_forward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st)
+                   : stfd::launch_band_forward<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st),
+               "forward sweep");
+    }
+    {
+        StageTimer tm(p, STFD_ST_SWEEP_BWD, st);
+        HIPCHK(f32 ? stfd::launch_band_backward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, Z, st)
+                   : stfd::launch_band_backward<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, Z, st),
+               "backward sweep");
+    }
+    return STFD_OK;
+}
 
 // one FD application: X (FP64 residual or load, Mx x Nt per RHS) -> U += alpha FD(X)
 int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t st) {
@@ -451,7 +526,10 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     g.batch = nrhs;
     stfd::GemmKind k1 = !f32 ? stfd::GEMM_D_D_STORE_D
                              : (p->opts.fwd_fp64 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_F_STORE_F);
-    HIPCHK(stfd::launch_gemm(k1, g, st), "forward transform 1");
+    {
+        StageTimer tm(p, STFD_ST_FWD1, st);
+        HIPCHK(stfd::launch_gemm(k1, g, st), "forward transform 1");
+    }
     // step 2b: G = T1 W2   (Mx x 2nsys)
     g = stfd::GemmArgs{};
     g.A = p->d_T1; g.B = p->d_W2; g.C = p->d_G;
@@ -459,12 +537,14 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * 2 * ns;
     g.batch = nrhs;
-    HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_STORE_F : stfd::GEMM_D_D_STORE_D, g, st), "forward transform 2");
+    {
+        StageTimer tm(p, STFD_ST_FWD2, st);
+        HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
+               "forward transform 2");
+    }
     // step 3: spatial solves, in place in G
-    if (f32)
-        HIPCHK(stfd::launch_band_sweeps<float>(p->d_LB, Mx, p->bp, ns, nrhs, p->d_G, p->d_G, st), "band sweeps");
-    else
-        HIPCHK(stfd::launch_band_sweeps<double>(p->d_LB, Mx, p->bp, ns, nrhs, p->d_G, p->d_G, st), "band sweeps");
+    int rc = spatial_sweeps(p, nrhs, p->d_G, p->d_G, st);
+    if (rc) return rc;
     // step 4: U += Re(Z Xb)
     g = stfd::GemmArgs{};
     g.A = p->d_G; g.B = p->d_Xb; g.C = U;
@@ -472,24 +552,38 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     g.lda = Mx; g.ldb = Nt; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * ns; g.strideC = (long long)Mx * Nt;
     g.batch = nrhs; g.alpha = 1.0;
-    HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_ADD_D : stfd::GEMM_D_D_ADD_D, g, st), "back transform");
+    {
+        StageTimer tm(p, STFD_ST_BACK, st);
+        HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_ADD_D : stfd::GEMM_D_D_ADD_D, g, st), "back transform");
+    }
     return STFD_OK;
 }
 
 // R = F - K_h U and squared norms (device) for nrhs blocks
 int residual(stfd_problem* p, int nrhs, const double* F, const double* U, double* R, hipStream_t st) {
     const int Mx = p->Mx, Nt = p->Nt;
-    HIPCHK(stfd::launch_spatial_apply(Mx, Nt, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA, U, p->d_P, st),
-           "spatial operator");
+    {
+        StageTimer tm(p, STFD_ST_SPATIAL, st);
+        HIPCHK(stfd::launch_spatial_apply(Mx, Nt, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA, U, p->d_P,
+                                          st),
+               "spatial operator");
+    }
     stfd::GemmArgs g{};
     g.A = p->d_P; g.B = p->d_Bres; g.C = R; g.F = F; g.partial = p->d_part;
     g.M = Mx; g.N = Nt; g.K = 2 * Nt;
     g.lda = Mx; g.ldb = Nt; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * Nt; g.strideF = (long long)Mx * Nt;
     g.batch = nrhs;
-    HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_RESID, g, st), "residual");
-    HIPCHK(stfd::launch_reduce_partials(p->d_part, stfd::gemm_resid_partials(Mx, Nt, 1), nrhs, p->d_norms, st),
-           "residual norms");
+    {
+        StageTimer tm(p, STFD_ST_RESID, st);
+        HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_RESID, g, st), "residual");
+    }
+    {
+        StageTimer tm(p, STFD_ST_REDUCE, st);
+        HIPCHK(stfd::launch_reduce_partials(p->d_part, stfd::gemm_resid_partials(Mx, Nt, 1), nrhs, p->d_norms,
+                                            st),
+               "residual norms");
+    }
     return STFD_OK;
 }
 
@@ -527,10 +621,8 @@ extern "C" int stfd_spatial_solve(stfd_problem* p, int nrhs, const void* G_dev, 
     if (!p || nrhs < 1 || !G_dev || !Z_dev) return fail(STFD_EINVAL, "spatial_solve: bad arguments");
     if (!p->factored) return fail(STFD_ESTATE, "spatial_solve: call stfd_fd_factor first");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    if (is_fp32(p))
-        HIPCHK(stfd::launch_band_sweeps<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G_dev, Z_dev, st), "sweeps");
-    else
-        HIPCHK(stfd::launch_band_sweeps<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G_dev, Z_dev, st), "sweeps");
+    int rc = spatial_sweeps(p, nrhs, G_dev, Z_dev, st);
+    if (rc) return rc;
     stfd::clear_error();
     return STFD_OK;
 }
@@ -587,6 +679,10 @@ extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, dou
         }
         X = p->d_R;
     }
+    if (p->prof_on) {
+        rc = drain_profile(p);
+        if (rc) return rc;
+    }
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = r;
     if (status == STFD_ENUMERIC) return fail(STFD_ENUMERIC, "fd_solve: non-finite residual");
@@ -595,8 +691,32 @@ extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, dou
     return STFD_OK;
 }
 
+extern "C" int stfd_profile(stfd_problem* p, int enable) {
+    if (!p) return fail(STFD_EINVAL, "profile: null problem");
+    int rc = drain_profile(p);
+    if (rc) return rc;
+    p->prof_on = enable != 0;
+    for (int i = 0; i < STFD_NSTAGE; ++i) {
+        p->prof_ms[i] = 0.0;
+        p->prof_cnt[i] = 0;
+    }
+    return STFD_OK;
+}
+
+extern "C" int stfd_profile_read(stfd_problem* p, double* ms, long long* counts) {
+    if (!p || !ms || !counts) return fail(STFD_EINVAL, "profile_read: bad arguments");
+    int rc = drain_profile(p);
+    if (rc) return rc;
+    for (int i = 0; i < STFD_NSTAGE; ++i) {
+        ms[i] = p->prof_ms[i];
+        counts[i] = p->prof_cnt[i];
+    }
+    return STFD_OK;
+}
+
 extern "C" void stfd_problem_free(stfd_problem* p) {
     if (!p) return;
+    for (auto e : p->ev_pool) (void)hipEventDestroy(e);
     free_work(p);
     (void)hipFree(p->d_rowptr);
     (void)hipFree(p->d_col);

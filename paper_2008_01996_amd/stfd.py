@@ -25,7 +25,11 @@ EXPORTED = [
     "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_fd_setup",
     "stfd_fd_setup_report", "stfd_fd_factor", "stfd_fd_solve", "stfd_kh_residual",
     "stfd_problem_free", "stfd_fd_apply", "stfd_spatial_solve", "stfd_system_lambdas",
+    "stfd_profile", "stfd_profile_read",
 ]
+
+STAGES = ["band_init", "band_ldl", "fwd1", "fwd2", "sweep_fwd", "sweep_bwd", "back", "spatial", "resid",
+          "reduce"]
 
 
 class StfdError(RuntimeError):
@@ -92,6 +96,8 @@ def lib():
         L.stfd_fd_apply.argtypes = [vp, C.c_int, vp, vp, vp]
         L.stfd_spatial_solve.argtypes = [vp, C.c_int, vp, vp, vp]
         L.stfd_system_lambdas.argtypes = [vp, dp]
+        L.stfd_profile.argtypes = [vp, C.c_int]
+        L.stfd_profile_read.argtypes = [vp, dp, C.POINTER(C.c_longlong)]
         L.stfd_problem_free.argtypes = [vp]
         L.stfd_problem_free.restype = None
         _LIB = L
@@ -268,6 +274,17 @@ class Problem:
         lam = np.empty(2 * n)
         _check(lib().stfd_system_lambdas(self._h, _dp(lam)))
         return lam[0::2] + 1j * lam[1::2]
+
+    def profile(self, enable=True):
+        """Enable (and clear) or disable per-stage event timing."""
+        _check(lib().stfd_profile(self._h, int(bool(enable))))
+
+    def profile_read(self):
+        """{stage: (total ms, launches)} since the last clear."""
+        ms = np.zeros(len(STAGES))
+        cnt = (C.c_longlong * len(STAGES))()
+        _check(lib().stfd_profile_read(self._h, _dp(ms), cnt))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(STAGES)}
 
     def kh_residual(self, F, U, R, stream=None):
         """R = F - K_h U on the device; returns (||R||^2, ||F||^2) per RHS."""
