@@ -72,6 +72,30 @@ __device__ __forceinline__ typename vec4<T>::type zero4() {
     return z;
 }
 
+// value of lane l (uniform) broadcast to the whole wave through a scalar
+// register (v_readlane), without an LDS round trip
+__device__ __forceinline__ float lane_bcast(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+    const unsigned long long x = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x & 0xffffffffull), l);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// lane k of this lane's group of G consecutive lanes (64 / G groups per wave)
+template <int G, typename T>
+__device__ __forceinline__ T group_bcast(T v, int k, int grp) {
+    T r = lane_bcast(v, k);
+#pragma unroll
+    for (int g = 1; g < 64 / G; ++g) {
+        const T o = lane_bcast(v, g * G + k);
+        if (grp == g) r = o;
+    }
+    return r;
+}
+
 // block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024)
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);

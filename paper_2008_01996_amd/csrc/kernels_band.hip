@@ -107,18 +107,18 @@ __global__ void __launch_bounds__(256) band_ldl_kernel(cplx<T>* __restrict__ LB,
                 PI[k * bp1 + d] = v.im;
             }
             __syncthreads();
-            // later panel columns k2 > k: A[k2 + d2, k2] -= L[k2+d2, k] D_k L[k2, k]
-            const int rest = nb - 1 - k;
-            for (int q = tid; q < rest * bp1; q += blockDim.x) {
-                const int k2 = k + 1 + q / bp1;
-                const int d2 = q % bp1;
-                const int dd = (k2 - k) + d2;           // row offset from column k
-                if (dd <= bp) {
-                    const cplx<T> lk2 = {PR[k * bp1 + (k2 - k)], PI[k * bp1 + (k2 - k)]};
-                    const cplx<T> lr = {PR[k * bp1 + dd], PI[k * bp1 + dd]};
-                    const cplx<T> t = cmul(cmul(lr, dk), lk2);
-                    PR[k2 * bp1 + d2] -= t.re;
-                    PI[k2 * bp1 + d2] -= t.im;
+            // later panel columns k2 > k: A[k2 + d2, k2] -= L[k2+d2, k] D_k L[k2, k];
+            // lane bits 0-3 pick the column, the rest stride down the rows
+            {
+                const int k2 = k + 1 + (tid & 15);
+                if (k2 < nb) {
+                    const int off = k2 - k;              // row offset of k2 from column k
+                    const cplx<T> dl = cmul(dk, cplx<T>{PR[k * bp1 + off], PI[k * bp1 + off]});
+                    for (int d2 = tid >> 4; d2 + off <= bp; d2 += 16) {
+                        const cplx<T> t = cmul(cplx<T>{PR[k * bp1 + off + d2], PI[k * bp1 + off + d2]}, dl);
+                        PR[k2 * bp1 + d2] -= t.re;
+                        PI[k2 * bp1 + d2] -= t.im;
+                    }
                 }
             }
             __syncthreads();
@@ -127,54 +127,77 @@ __global__ void __launch_bounds__(256) band_ldl_kernel(cplx<T>* __restrict__ LB,
         cplx<T>* dst = base + (size_t)p0 * bp1;
         for (int e = tid; e < nb * bp1; e += blockDim.x) dst[e] = cplx<T>{PR[e], PI[e]};
         // ---- trailing update on the matrix cores
-        // tile (ti, tj), ti >= tj: rows r0 = p0 + 16 + 16 ti, columns c0 = p0 + 16 + 16 tj
-        for (int t = wave; t < tiles_total; t += 4) {
-            // map linear t to (ti, tj) with tj <= ti
-            int ti = 0;
-            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-            const int tj = t - ti * (ti + 1) / 2;
-            const int r0 = p0 + 16 + 16 * ti;
-            const int c0 = p0 + 16 + 16 * tj;
-            if (c0 >= Mx || r0 >= Mx) continue;
-            typename vec4<T>::type accR = zero4<T>(), accI = zero4<T>();
-            const int li = lane & 15, lk = lane >> 4;
+        // tile (ti, tj), ti >= tj: rows r0 = p0 + 16 + 16 ti, columns c0 = p0 + 16 + 16 tj.
+        // Each wave takes every 4th tile, CH tiles at a time: all their global
+        // loads are issued before the first MFMA so the latency is paid once
+        // per chunk.
+        constexpr int CH = 8;
+        const int li = lane & 15, lk = lane >> 4;
+        for (int tbase = wave; tbase < tiles_total; tbase += 4 * CH) {
+            cplx<T> cv[CH][4];
+            int rr0[CH], cc0[CH];
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = 4 * kk + lk;
-                // A operand: L[c', k] with c' = c0 + li  (offset c' - p0 - k)
-                // B operand: L[r, k] D[k] with r = r0 + li
-                T ar = 0, ai = 0, br = 0, bi = 0;
-                if (k < nb) {
-                    const int oc = c0 + li - p0 - k;
-                    if (oc >= 1 && oc <= bp) {
-                        ar = PR[k * bp1 + oc];
-                        ai = PI[k * bp1 + oc];
-                    }
-                    const int orr = r0 + li - p0 - k;
-                    if (orr >= 1 && orr <= bp) {
-                        const cplx<T> l = {PR[k * bp1 + orr], PI[k * bp1 + orr]};
-                        const cplx<T> ld = cmul(l, cplx<T>{DR[k], DI[k]});
-                        br = ld.re;
-                        bi = ld.im;
-                    }
+            for (int u = 0; u < CH; ++u) {
+                const int t = tbase + 4 * u;
+                rr0[u] = Mx;
+                cc0[u] = Mx;
+                if (t < tiles_total) {
+                    int ti = 0;
+                    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+                    const int tj = t - ti * (ti + 1) / 2;
+                    rr0[u] = p0 + 16 + 16 * ti;
+                    cc0[u] = p0 + 16 + 16 * tj;
                 }
-                accR = mfma16x16x4<T>(ar, br, accR);
-                accR = mfma16x16x4<T>(-ai, bi, accR);
-                accI = mfma16x16x4<T>(ar, bi, accI);
-                accI = mfma16x16x4<T>(ai, br, accI);
-            }
-            // D[c' = c0 + mfma_row(lk, j)][r = r0 + li]
-            const int r = r0 + li;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = c0 + mfma_row<T>(lk, j);
-                const int d = r - c;
-                if (r < Mx && c < Mx && d >= 0 && d <= bp) {
-                    cplx<T>* p = base + (size_t)c * bp1 + d;
-                    cplx<T> v = *p;
-                    v.re -= accR[j];
-                    v.im -= accI[j];
-                    *p = v;
+                for (int j = 0; j < 4; ++j) {
+                    const int r = rr0[u] + li, c = cc0[u] + mfma_row<T>(lk, j);
+                    const int d = r - c;
+                    cv[u][j] = cplx<T>{T(0), T(0)};
+                    if (r < Mx && c < Mx && d >= 0 && d <= bp) cv[u][j] = base[(size_t)c * bp1 + d];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                if (cc0[u] >= Mx || rr0[u] >= Mx) continue;
+                typename vec4<T>::type accR = zero4<T>(), accI = zero4<T>();
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    // A operand: L[c', k] with c' = c0 + li; B operand: L[r, k] D[k], r = r0 + li
+                    T ar = 0, ai = 0, br = 0, bi = 0;
+                    if (k < nb) {
+                        const int oc = cc0[u] + li - p0 - k;
+                        if (oc >= 1 && oc <= bp) {
+                            ar = PR[k * bp1 + oc];
+                            ai = PI[k * bp1 + oc];
+                        }
+                        const int orr = rr0[u] + li - p0 - k;
+                        if (orr >= 1 && orr <= bp) {
+                            const cplx<T> l = {PR[k * bp1 + orr], PI[k * bp1 + orr]};
+                            const cplx<T> ld = cmul(l, cplx<T>{DR[k], DI[k]});
+                            br = ld.re;
+                            bi = ld.im;
+                        }
+                    }
+                    accR = mfma16x16x4<T>(ar, br, accR);
+                    accR = mfma16x16x4<T>(-ai, bi, accR);
+                    accI = mfma16x16x4<T>(ar, bi, accI);
+                    accI = mfma16x16x4<T>(ai, br, accI);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    cv[u][j].re -= accR[j];
+                    cv[u][j].im -= accI[j];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    // D[c' = c0 + mfma_row(lk, j)][r = r0 + li]
+                    const int r = rr0[u] + li, c = cc0[u] + mfma_row<T>(lk, j);
+                    const int d = r - c;
+                    if (r < Mx && c < Mx && d >= 0 && d <= bp) base[(size_t)c * bp1 + d] = cv[u][j];
                 }
             }
         }

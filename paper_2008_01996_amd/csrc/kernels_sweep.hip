@@ -31,53 +31,55 @@ constexpr int NT = 256;     // threads per workgroup
 constexpr int NRS = 16;     // right-hand sides per workgroup
 constexpr int BPMAX = 256;  // largest padded half-bandwidth
 
-constexpr int ept_for(int cb) { return (cb * (BPMAX + 1) + NT - 1) / NT; }   // block elements per thread
+constexpr int ept_for(int cb, int bpc) { return (cb * (bpc + 1) + NT - 1) / NT; }   // block elements per thread
 
-// issue the global loads of one block (CB columns) into registers
+// issue the global loads of one block (CB columns) into registers; branch-free
+// (clamped addresses, masked values) so that the waits on them can be partial
 template <typename T, int CB, int EPT>
 __device__ __forceinline__ void load_block(cplx<T> (&r)[EPT], const cplx<T>* base, int blk, int nblk, int Mx,
                                            int bp1) {
     const int tid = threadIdx.x;
-    if (blk < 0 || blk >= nblk) return;
-    const int c0 = blk * CB;
-    const int nbv = min(CB, Mx - c0);
-    const int ne = nbv * bp1;
+    const int b = min(max(blk, 0), nblk - 1);
+    const int c0 = b * CB;
+    const int ne = min(CB, Mx - c0) * bp1;
+    const bool live = blk >= 0 && blk < nblk;
     const cplx<T>* src = base + (size_t)c0 * bp1;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int e = tid + NT * j;
-        r[j] = (e < ne) ? src[e] : cplx<T>{T(0), T(0)};
+        const cplx<T> v = src[min(e, ne - 1)];
+        const bool ok = live && e < ne;
+        r[j].re = ok ? v.re : T(0);
+        r[j].im = ok ? v.im : T(0);
     }
 }
 
+// LDS block buffers hold EPT * NT entries so that staging needs no bounds test
 template <typename T, int CB, int EPT>
-__device__ __forceinline__ void stage_block(const cplx<T> (&r)[EPT], T* LR, T* LI, int bp1) {
+__device__ __forceinline__ void stage_block(const cplx<T> (&r)[EPT], T* LR, T* LI) {
     const int tid = threadIdx.x;
-    const int ne = CB * bp1;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const int e = tid + NT * j;
-        if (e < ne) {
-            LR[e] = r[j].re;
-            LI[e] = r[j].im;
-        }
+        LR[e] = r[j].re;
+        LI[e] = r[j].im;
     }
 }
 
 }  // namespace
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int PD>
+template <typename T, int CB, int PD, int BPC>
 __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp, int nsys,
                                                            int nrhs, const T* __restrict__ G, T* __restrict__ W) {
-    constexpr int EPT = ept_for(CB);
+    constexpr int EPT = ept_for(CB, BPC);
     constexpr int GROUPS = NT / CB;        // right-hand sides per diagonal pass
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
     const int ring = bp + CB;
-    T* LR = reinterpret_cast<T*>(smem_raw);       // [CB][bp1]
-    T* LI = LR + CB * bp1;
-    T* QR = LI + CB * bp1;                        // ring [ring][NRS]
+    T* LR = reinterpret_cast<T*>(smem_raw);       // [CB][bp1] (EPT * NT entries)
+    T* LI = LR + EPT * NT;
+    T* QR = LI + EPT * NT;                        // ring [ring][NRS]
     T* QI = QR + ring * NRS;
     T* YR = QI + ring * NRS;                      // [CB][NRS]
     T* YI = YR + CB * NRS;
@@ -109,38 +111,43 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         QI[q] = im;
     }
 
+    int cs = 0;                           // c0 mod ring, kept incrementally
+    auto wrap = [ring](int x) { return x >= ring ? x - ring : x; };
     for (int i0 = 0; i0 < nblk; i0 += PD) {
 #pragma unroll
         for (int s = 0; s < PD; ++s) {
+            // blocks past the end are empty (nb = 0) so the loop stays uniform
             const int blk = i0 + s;
-            if (blk >= nblk) break;
             const int c0 = blk * CB;
-            const int nb = min(CB, Mx - c0);
-            stage_block<T, CB, EPT>(regs[s], LR, LI, bp1);
-            load_block<T, CB, EPT>(regs[s], base, blk + PD, nblk, Mx, bp1);
+            const int nb = max(0, min(CB, Mx - c0));
             // right-hand sides of the rows entering the window after this block
+            // (issued before the prefetch below, so waiting for them later
+            // does not drain it)
             T ent_re[(CB * NRS + NT - 1) / NT], ent_im[(CB * NRS + NT - 1) / NT];
 #pragma unroll
             for (int j = 0; j < (CB * NRS + NT - 1) / NT; ++j) {
                 const int q = tid + NT * j;
                 const int row = c0 + ring + q / NRS, t = q % NRS;
-                ent_re[j] = 0;
-                ent_im[j] = 0;
-                if (q < CB * NRS && row < Mx && t < nr) {
-                    ent_re[j] = gre[(size_t)t * rstride + row];
-                    ent_im[j] = gim[(size_t)t * rstride + row];
-                }
+                const bool ok = q < CB * NRS && row < Mx && t < nr;
+                const size_t off = ok ? (size_t)t * rstride + row : 0;
+                const T a = gre[off], b = gim[off];
+                ent_re[j] = ok ? a : T(0);
+                ent_im[j] = ok ? b : T(0);
             }
+            stage_block<T, CB, EPT>(regs[s], LR, LI);
+            load_block<T, CB, EPT>(regs[s], base, blk + PD, nblk, Mx, bp1);
             __syncthreads();
             // unit lower-triangular diagonal block: lane = row k2 of the block
             for (int t0 = 0; t0 < nr; t0 += GROUPS) {
                 const int k2 = tid % CB, t = t0 + tid / CB;
-                const int slot = ((c0 + k2) % ring) * NRS + min(t, NRS - 1);
+                const int slot = wrap(cs + k2) * NRS + min(t, NRS - 1);
                 T vr = QR[slot], vi = QI[slot];
-                const int gbase = (tid & 63) & ~(CB - 1);
-                for (int k = 0; k < nb; ++k) {
-                    const T yr = __shfl(vr, gbase | k, 64);
-                    const T yi = __shfl(vi, gbase | k, 64);
+                const int grp = (tid & 63) / CB;
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    if (k >= nb) continue;
+                    const T yr = group_bcast<CB>(vr, k, grp);
+                    const T yi = group_bcast<CB>(vi, k, grp);
                     if (k2 > k && k2 - k <= bp) {
                         const T lr = LR[k * bp1 + (k2 - k)], li = LI[k * bp1 + (k2 - k)];
                         vr -= lr * yr - li * yi;
@@ -164,20 +171,23 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                 }
             }
             // rows below the block: q[row] -= sum_k L[row, c0 + k] y_k
-            for (int q = tid; q < bp * nr; q += NT) {
-                const int rr = q % bp, t = q / bp;
+            for (int t = 0; t < nr; ++t)
+            for (int rr = tid; rr < bp; rr += NT) {
                 const int row = c0 + CB + rr;
                 if (row >= Mx) continue;
                 T ar = 0, ai = 0;
-                const int kmin = max(0, row - c0 - bp);
-                for (int k = kmin; k < nb; ++k) {
-                    const int d = row - c0 - k;
+                const int kmin = row - c0 - bp;
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    // fully unrolled with masked terms: all LDS reads issue together
+                    const int d = min(max(row - c0 - k, 0), bp);
+                    const bool on = k < nb && k >= kmin;
                     const T lr = LR[k * bp1 + d], li = LI[k * bp1 + d];
-                    const T yr = YR[k * NRS + t], yi = YI[k * NRS + t];
+                    const T yr = on ? YR[k * NRS + t] : T(0), yi = on ? YI[k * NRS + t] : T(0);
                     ar += lr * yr - li * yi;
                     ai += lr * yi + li * yr;
                 }
-                const int slot = (row % ring) * NRS + t;
+                const int slot = wrap(cs + CB + rr) * NRS + t;
                 QR[slot] -= ar;
                 QI[slot] -= ai;
             }
@@ -186,28 +196,29 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
             for (int j = 0; j < (CB * NRS + NT - 1) / NT; ++j) {
                 const int q = tid + NT * j;
                 if (q < CB * NRS) {
-                    const int row = c0 + ring + q / NRS, t = q % NRS;
-                    QR[(row % ring) * NRS + t] = ent_re[j];
-                    QI[(row % ring) * NRS + t] = ent_im[j];
+                    const int slot = wrap(cs + q / NRS) * NRS + q % NRS;
+                    QR[slot] = ent_re[j];
+                    QI[slot] = ent_im[j];
                 }
             }
+            cs = wrap(cs + CB);
             __syncthreads();
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int PD>
+template <typename T, int CB, int PD, int BPC>
 __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp,
                                                             int nsys, int nrhs, T* __restrict__ W) {
-    constexpr int EPT = ept_for(CB);
+    constexpr int EPT = ept_for(CB, BPC);
     constexpr int GROUPS = NT / CB;
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
     const int ring = bp + CB;
-    T* LR = reinterpret_cast<T*>(smem_raw);       // [CB][bp1]
-    T* LI = LR + CB * bp1;
-    T* ZR = LI + CB * bp1;                        // ring [ring][NRS] of finished z
+    T* LR = reinterpret_cast<T*>(smem_raw);       // [CB][bp1] (EPT * NT entries)
+    T* LI = LR + EPT * NT;
+    T* ZR = LI + EPT * NT;                        // ring [ring][NRS] of finished z
     T* ZI = ZR + ring * NRS;
     T* SR = ZI + ring * NRS;                      // [CB][NRS] off-block sums
     T* SI = SR + CB * NRS;
@@ -222,7 +233,8 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
     const int nblk = (Mx + CB - 1) / CB;
     // (row, rhs) dot products split over `parts` lanes
     const int parts = max(1, NT / (CB * max(nr, 1)));
-    const int pw = parts >= 8 ? 8 : parts >= 4 ? 4 : parts >= 2 ? 2 : 1;
+    const int lpw = parts >= 8 ? 3 : parts >= 4 ? 2 : parts >= 2 ? 1 : 0;
+    const int pw = 1 << lpw;
 
     for (int q = tid; q < ring * NRS; q += NT) {
         ZR[q] = 0;
@@ -232,27 +244,47 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
 #pragma unroll
     for (int s = 0; s < PD; ++s) load_block<T, CB, EPT>(regs[s], base, nblk - 1 - s, nblk, Mx, bp1);
 
+    int cs = ((nblk - 1) * CB) % ring;    // c0 mod ring, kept incrementally
+    auto wrap = [ring](int x) { return x >= ring ? x - ring : x; };
     for (int i0 = 0; i0 < nblk; i0 += PD) {
 #pragma unroll
         for (int s = 0; s < PD; ++s) {
+            // iterations past the first block are empty (nb = 0): uniform loop
             const int it = i0 + s;
-            if (it >= nblk) break;
             const int blk = nblk - 1 - it;
             const int c0 = blk * CB;
-            const int nb = min(CB, Mx - c0);
-            stage_block<T, CB, EPT>(regs[s], LR, LI, bp1);
+            const int nb = blk >= 0 ? min(CB, Mx - c0) : 0;
+            // w of the block's rows, one (row, rhs) pair per lane and pass,
+            // issued before the prefetch below
+            constexpr int NP = (CB * NRS + NT - 1) / NT;
+            T wv_re[NP], wv_im[NP];
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                const int q = tid + NT * j;
+                const int kp = q % CB, t = q / CB;
+                const bool ok = kp < nb && t < nr;
+                const size_t off = ok ? (size_t)t * rstride + c0 + kp : 0;
+                const T a = wre[off], b = wim[off];
+                wv_re[j] = ok ? a : T(0);
+                wv_im[j] = ok ? b : T(0);
+            }
+            stage_block<T, CB, EPT>(regs[s], LR, LI);
             load_block<T, CB, EPT>(regs[s], base, blk - PD, nblk, Mx, bp1);
             __syncthreads();
             // off-block sums for rows c0 + k, k < nb
             {
-                const int item = tid / pw, part = tid % pw;
+                const int item = tid >> lpw, part = tid & (pw - 1);
                 const int k = item % CB, t = item / CB;
                 T ar = 0, ai = 0;
                 if (k < nb && t < nr && item < CB * NRS) {
-                    for (int d = (nb - k) + part; d <= bp; d += pw) {
+                    const int d0 = (nb - k) + part;
+                    int rs = wrap(cs + k + d0);
+                    for (int d = d0; d <= bp; d += pw) {
                         const int row = c0 + k + d;
                         if (row >= Mx) break;
-                        const int slot = (row % ring) * NRS + t;
+                        const int slot = rs * NRS + t;
+                        rs += pw;
+                        if (rs >= ring) rs -= ring;
                         const T lr = LR[k * bp1 + d], li = LI[k * bp1 + d];
                         const T zr = ZR[slot], zi = ZI[slot];
                         ar += lr * zr - li * zi;
@@ -268,14 +300,16 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                     SI[k * NRS + t] = ai;
                 }
                 // items beyond one pass (many right-hand sides): plain loop
-                for (int it2 = NT / pw + item; it2 < CB * nr; it2 += NT / pw) {
+                for (int it2 = (NT >> lpw) + item; it2 < CB * nr; it2 += (NT >> lpw)) {
                     const int k3 = it2 % CB, t3 = it2 / CB;
                     T br = 0, bi = 0;
                     if (k3 < nb) {
+                        int rs3 = wrap(cs + k3 + (nb - k3) + part);
                         for (int d = (nb - k3) + part; d <= bp; d += pw) {
                             const int row = c0 + k3 + d;
                             if (row >= Mx) break;
-                            const int slot = (row % ring) * NRS + t3;
+                            const int slot = rs3 * NRS + t3;
+                            rs3 = wrap(rs3 + pw);
                             const T lr = LR[k3 * bp1 + d], li = LI[k3 * bp1 + d];
                             const T zr = ZR[slot], zi = ZI[slot];
                             br += lr * zr - li * zi;
@@ -294,26 +328,32 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
             }
             __syncthreads();
             // diagonal block, descending rows; lane = row k' of the block
-            for (int t0 = 0; t0 < nr; t0 += GROUPS) {
+#pragma unroll
+            for (int pass = 0; pass < NP; ++pass) {
+                const int t0 = pass * GROUPS;
+                if (t0 >= nr) break;
                 const int kp = tid % CB, t = t0 + tid / CB;
                 const bool live = kp < nb && t < nr;
                 T vr = 0, vi = 0;
                 if (live) {
-                    vr = wre[(size_t)t * rstride + c0 + kp] - SR[kp * NRS + t];
-                    vi = wim[(size_t)t * rstride + c0 + kp] - SI[kp * NRS + t];
+                    vr = wv_re[pass] - SR[kp * NRS + t];
+                    vi = wv_im[pass] - SI[kp * NRS + t];
                 }
-                const int gbase = (tid & 63) & ~(CB - 1);
-                for (int k = nb - 1; k >= 0; --k) {
-                    const T zr = __shfl(vr, gbase | k, 64);
-                    const T zi = __shfl(vi, gbase | k, 64);
+                const int grp = (tid & 63) / CB;
+#pragma unroll
+                for (int kk = 0; kk < CB; ++kk) {
+                    const int k = CB - 1 - kk;
+                    if (k >= nb) continue;
+                    const T zr = group_bcast<CB>(vr, k, grp);
+                    const T zi = group_bcast<CB>(vi, k, grp);
                     if (kp < k && k - kp <= bp) {
                         const T lr = LR[kp * bp1 + (k - kp)], li = LI[kp * bp1 + (k - kp)];
                         vr -= lr * zr - li * zi;
                         vi -= lr * zi + li * zr;
                     }
                 }
-                if (t < NRS) {
-                    const int slot = ((c0 + kp) % ring) * NRS + t;
+                if (t < NRS && nb > 0) {
+                    const int slot = wrap(cs + kp) * NRS + t;
                     ZR[slot] = live ? vr : T(0);
                     ZI[slot] = live ? vi : T(0);
                 }
@@ -322,67 +362,66 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                     wim[(size_t)t * rstride + c0 + kp] = vi;
                 }
             }
+            cs = cs >= CB ? cs - CB : cs - CB + ring;
             __syncthreads();
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB>
+template <typename T, int CB, int BPC>
 static size_t sweep_smem_cb(int bp) {
-    return (2 * (size_t)CB * (bp + 1) + 2 * (size_t)(bp + CB) * NRS + 2 * (size_t)CB * NRS) * sizeof(T);
+    return (2 * (size_t)ept_for(CB, BPC) * NT + 2 * (size_t)(bp + CB) * NRS + 2 * (size_t)CB * NRS) * sizeof(T);
 }
 
 template <typename T>
 size_t sweep_smem(int bp) {
-    return sweep_smem_cb<T, 16>(bp);    // the smaller configuration always fits if this does
+    return bp <= 128 ? sweep_smem_cb<T, 32, 128>(bp) : sweep_smem_cb<T, 16, 256>(bp);
 }
 
-template <typename T, int CB, int PD>
+template <typename T, int CB, int PD, int BPC>
 static hipError_t launch_fwd(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
                              hipStream_t st) {
-    const size_t smem = sweep_smem_cb<T, CB>(bp);
-    hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, PD>,
+    const size_t smem = sweep_smem_cb<T, CB, BPC>(bp);
+    hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, PD, BPC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
-    hipLaunchKernelGGL((sweep_forward_kernel<T, CB, PD>), grid, dim3(NT), smem, st,
+    hipLaunchKernelGGL((sweep_forward_kernel<T, CB, PD, BPC>), grid, dim3(NT), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<const T*>(G),
                        static_cast<T*>(W));
     return hipGetLastError();
 }
 
-template <typename T, int CB, int PD>
+template <typename T, int CB, int PD, int BPC>
 static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
-    const size_t smem = sweep_smem_cb<T, CB>(bp);
-    hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, PD>,
+    const size_t smem = sweep_smem_cb<T, CB, BPC>(bp);
+    hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, PD, BPC>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
-    hipLaunchKernelGGL((sweep_backward_kernel<T, CB, PD>), grid, dim3(NT), smem, st,
+    hipLaunchKernelGGL((sweep_backward_kernel<T, CB, PD, BPC>), grid, dim3(NT), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W));
     return hipGetLastError();
 }
 
-// Column block 32 while it fits in LDS (fewer block steps), else 16.  The
-// prefetch depth keeps about two blocks of FP32 or one of FP64 in registers.
+// bp <= 128: column blocks of 32 with 3 (FP32) or 2 (FP64) blocks in flight;
+// bp <= 256: blocks of 16 with 3 / 2 in flight.
 template <typename T>
 hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
                                hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
-    constexpr int PD32 = sizeof(T) == 4 ? 2 : 1;
-    if (sweep_smem_cb<T, 32>(bp) <= 160 * 1024 && bp <= 128)
-        return launch_fwd<T, 32, PD32>(LB, Mx, bp, nsys, nrhs, G, W, st);
-    return launch_fwd<T, 16, 2>(LB, Mx, bp, nsys, nrhs, G, W, st);
+    constexpr int PD = sizeof(T) == 4 ? 3 : 2;
+    if (bp <= 128) return launch_fwd<T, 32, PD, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
+    return launch_fwd<T, 16, PD, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
 }
 
 template <typename T>
 hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
-    constexpr int PD32 = sizeof(T) == 4 ? 2 : 1;
-    if (sweep_smem_cb<T, 32>(bp) <= 160 * 1024 && bp <= 128)
-        return launch_bwd<T, 32, PD32>(LB, Mx, bp, nsys, nrhs, W, st);
-    return launch_bwd<T, 16, 2>(LB, Mx, bp, nsys, nrhs, W, st);
+    constexpr int PD = sizeof(T) == 4 ? 3 : 2;
+    if (bp <= 128) return launch_bwd<T, 32, PD, 128>(LB, Mx, bp, nsys, nrhs, W, st);
+    return launch_bwd<T, 16, PD, 256>(LB, Mx, bp, nsys, nrhs, W, st);
 }
 
 template hipError_t launch_band_forward<float>(const void*, int, int, int, int, const void*, void*, hipStream_t);
