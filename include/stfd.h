@@ -62,9 +62,13 @@ typedef struct stfd_batch stfd_batch;
 
 typedef struct {
     int precision;        /* STFD_PREC_FP64 or STFD_PREC_FP32 (default FP32) */
-    int fwd_fp64;         /* FP32 precision only: run the first forward GEMM
-                             (F^ A_t^-1 conj(U_t) Sigma^-1) in FP64 (1, default)
-                             or in FP32 (0) */
+    int fp64_transforms;  /* FP32 precision only: bit mask of the transform GEMMs
+                             computed with FP64 matrix cores on FP32-stored data:
+                             bit 0 = first forward GEMM (F^ A_t^-1 conj(U_t) Sigma^-1),
+                             bit 1 = second forward GEMM (x V_t^T),
+                             bit 2 = back transform (Z X^T, update of U).
+                             Default 5 (first forward GEMM and back transform:
+                             their FP32 rounding is amplified by kappa_2(X_t)). */
     double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
     int max_refine;       /* maximum number of refinement corrections (default 30) */
 } stfd_opts;

@@ -28,7 +28,7 @@ extern "C" const char* stfd_last_error(void) { return stfd::last_error(); }
 extern "C" int stfd_opts_default(stfd_opts* o) {
     if (!o) return fail(STFD_EINVAL, "null opts");
     o->precision = STFD_PREC_FP32;
-    o->fwd_fp64 = 1;
+    o->fp64_transforms = 5;
     o->rtol = 1e-10;
     o->max_refine = 30;
     return STFD_OK;

@@ -35,6 +35,8 @@ enum GemmKind {
     GEMM_F_F_ADD_D,     // FP32 MFMA, FP64 accumulate into C
     GEMM_D_D_ADD_D,     // FP64 MFMA, FP64 accumulate into C
     GEMM_D_D_RESID,     // FP64 residual
+    GEMM_F_D_STORE_F,   // FP32 A widened to FP64, FP64 B, FP64 MFMA, FP32 out
+    GEMM_F_D_ADD_D,     // FP32 A widened to FP64, FP64 B, FP64 MFMA, FP64 accumulate into C
 };
 
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& g, hipStream_t st);

@@ -132,6 +132,8 @@ hipError_t launch_gemm(GemmKind kind, const GemmArgs& g, hipStream_t st) {
         case GEMM_F_F_ADD_D: return launch_gemm_t<float, float, EPI_ADD_F64>(g, st);
         case GEMM_D_D_ADD_D: return launch_gemm_t<double, double, EPI_ADD_F64>(g, st);
         case GEMM_D_D_RESID: return launch_gemm_t<double, double, EPI_RESID>(g, st);
+        case GEMM_F_D_STORE_F: return launch_gemm_t<float, double, EPI_STORE_F32>(g, st);
+        case GEMM_F_D_ADD_D: return launch_gemm_t<float, double, EPI_ADD_F64>(g, st);
     }
     return hipErrorInvalidValue;
 }

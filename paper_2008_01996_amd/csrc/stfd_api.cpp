@@ -31,9 +31,11 @@ struct stfd_problem {
     double* d_valA = nullptr;
     double* d_lam = nullptr;
     double* d_W1 = nullptr;     // Nt x 2Nt  FP64: [Re | Im] of A_t^-1 conj(U_t) Sigma^-1
-    float* d_W1f = nullptr;     // FP32 copy (fwd_fp64 = 0)
-    void* d_W2 = nullptr;       // 2Nt x 2nsys  [[Re, Im], [-Im, Re]] of V_t^T[:, sys]
-    void* d_Xb = nullptr;       // 2nsys x Nt   [Re; -Im] of c_k x_k^T
+    float* d_W1f = nullptr;     // FP32 copy (first forward GEMM in FP32)
+    void* d_W2 = nullptr;       // 2Nt x 2nsys  [[Re, Im], [-Im, Re]] of V_t^T[:, sys], working precision
+    void* d_Xb = nullptr;       // 2nsys x Nt   [Re; -Im] of c_k x_k^T, working precision
+    double* d_W2d = nullptr;    // FP64 copies for FP64 transforms in the FP32 form
+    double* d_Xbd = nullptr;
     double* d_Bres = nullptr;   // 2Nt x Nt     [A_t^T; M_t^T]
     void* d_LB = nullptr;       // band factors
     int* d_flag = nullptr;
@@ -321,7 +323,7 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     stfd_opts_default(&o);
     if (opts) o = *opts;
     if ((o.precision != STFD_PREC_FP32 && o.precision != STFD_PREC_FP64) || !(o.rtol >= 0.0) || o.max_refine < 0 ||
-        o.max_refine >= STFD_MAX_HIST)
+        o.max_refine >= STFD_MAX_HIST || o.fp64_transforms < 0 || o.fp64_transforms > 7)
         return fail(STFD_EINVAL, "fd_setup: bad options");
     const auto t0 = std::chrono::steady_clock::now();
     Decomp D;
@@ -421,7 +423,9 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     if (f32) {
         if ((e = upload(&p->d_W1f, W1f.data(), W1f.size() * sizeof(float), st)) ||
             (e = upload(&p->d_W2, W2f.data(), W2f.size() * sizeof(float), st)) ||
-            (e = upload(&p->d_Xb, Xbf.data(), Xbf.size() * sizeof(float), st))) {
+            (e = upload(&p->d_Xb, Xbf.data(), Xbf.size() * sizeof(float), st)) ||
+            (e = upload(&p->d_W2d, W2h.data(), W2h.size() * sizeof(double), st)) ||
+            (e = upload(&p->d_Xbd, Xbh.data(), Xbh.size() * sizeof(double), st))) {
             stfd_problem_free(p);
             return e;
         }
@@ -518,28 +522,30 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     stfd::GemmArgs g{};
     // step 2a: T1 = X W1   (Mx x 2Nt)
     g.A = X;
-    g.B = (f32 && !p->opts.fwd_fp64) ? static_cast<const void*>(p->d_W1f) : static_cast<const void*>(p->d_W1);
+    const int mask = f32 ? p->opts.fp64_transforms : 7;
+    g.B = (f32 && !(mask & 1)) ? static_cast<const void*>(p->d_W1f) : static_cast<const void*>(p->d_W1);
     g.C = p->d_T1;
     g.M = Mx; g.N = 2 * Nt; g.K = Nt;
     g.lda = Mx; g.ldb = 2 * Nt; g.ldc = Mx;
     g.strideA = (long long)Mx * Nt; g.strideC = (long long)Mx * 2 * Nt;
     g.batch = nrhs;
-    stfd::GemmKind k1 = !f32 ? stfd::GEMM_D_D_STORE_D
-                             : (p->opts.fwd_fp64 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_F_STORE_F);
+    stfd::GemmKind k1 = !f32 ? stfd::GEMM_D_D_STORE_D : ((mask & 1) ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_F_STORE_F);
     {
         StageTimer tm(p, STFD_ST_FWD1, st);
         HIPCHK(stfd::launch_gemm(k1, g, st), "forward transform 1");
     }
     // step 2b: G = T1 W2   (Mx x 2nsys)
     g = stfd::GemmArgs{};
-    g.A = p->d_T1; g.B = p->d_W2; g.C = p->d_G;
+    g.A = p->d_T1; g.B = (f32 && (mask & 2)) ? static_cast<const void*>(p->d_W2d) : p->d_W2; g.C = p->d_G;
     g.M = Mx; g.N = 2 * ns; g.K = 2 * Nt;
     g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * 2 * ns;
     g.batch = nrhs;
     {
         StageTimer tm(p, STFD_ST_FWD2, st);
-        HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
+        HIPCHK(stfd::launch_gemm(!f32 ? stfd::GEMM_D_D_STORE_D
+                                       : ((mask & 2) ? stfd::GEMM_F_D_STORE_F : stfd::GEMM_F_F_STORE_F),
+                                 g, st),
                "forward transform 2");
     }
     // step 3: spatial solves, in place in G
@@ -547,14 +553,17 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     if (rc) return rc;
     // step 4: U += Re(Z Xb)
     g = stfd::GemmArgs{};
-    g.A = p->d_G; g.B = p->d_Xb; g.C = U;
+    g.A = p->d_G; g.B = (f32 && (mask & 4)) ? static_cast<const void*>(p->d_Xbd) : p->d_Xb; g.C = U;
     g.M = Mx; g.N = Nt; g.K = 2 * ns;
     g.lda = Mx; g.ldb = Nt; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * ns; g.strideC = (long long)Mx * Nt;
     g.batch = nrhs; g.alpha = 1.0;
     {
         StageTimer tm(p, STFD_ST_BACK, st);
-        HIPCHK(stfd::launch_gemm(f32 ? stfd::GEMM_F_F_ADD_D : stfd::GEMM_D_D_ADD_D, g, st), "back transform");
+        HIPCHK(stfd::launch_gemm(!f32 ? stfd::GEMM_D_D_ADD_D
+                                       : ((mask & 4) ? stfd::GEMM_F_D_ADD_D : stfd::GEMM_F_F_ADD_D),
+                                 g, st),
+               "back transform");
     }
     return STFD_OK;
 }
@@ -727,6 +736,8 @@ extern "C" void stfd_problem_free(stfd_problem* p) {
     (void)hipFree(p->d_W1f);
     (void)hipFree(p->d_W2);
     (void)hipFree(p->d_Xb);
+    (void)hipFree(p->d_W2d);
+    (void)hipFree(p->d_Xbd);
     (void)hipFree(p->d_Bres);
     (void)hipFree(p->d_LB);
     (void)hipFree(p->d_flag);

@@ -39,7 +39,7 @@ class StfdError(RuntimeError):
 
 
 class Opts(C.Structure):
-    _fields_ = [("precision", C.c_int), ("fwd_fp64", C.c_int), ("rtol", C.c_double),
+    _fields_ = [("precision", C.c_int), ("fp64_transforms", C.c_int), ("rtol", C.c_double),
                 ("max_refine", C.c_int)]
 
 
@@ -213,8 +213,11 @@ def _stream_ptr(stream):
 class Problem:
     """FD solver for one (space, time mesh) pair on the current GPU."""
 
-    def __init__(self, space: Space, At, Mt, precision="fp32", fwd_fp64=True, rtol=1e-10, max_refine=30,
+    def __init__(self, space: Space, At, Mt, precision="fp32", fp64_transforms=5, rtol=1e-10, max_refine=30,
                  stream=None):
+        """fp64_transforms (FP32 form only): bit mask of the transform GEMMs run
+        on FP64 matrix cores, bit 0 first forward, bit 1 second forward, bit 2
+        back transform."""
         self.space = space        # keep alive: the problem refers to it
         At = _f64(At)
         Mt = _f64(Mt)
@@ -223,7 +226,7 @@ class Problem:
         o = Opts()
         _check(lib().stfd_opts_default(C.byref(o)))
         o.precision = {"fp32": PREC_FP32, "fp64": PREC_FP64}[precision]
-        o.fwd_fp64 = int(bool(fwd_fp64))
+        o.fp64_transforms = int(fp64_transforms)
         o.rtol = float(rtol)
         o.max_refine = int(max_refine)
         self.precision = precision

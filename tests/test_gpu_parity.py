@@ -55,8 +55,9 @@ def _to_dev(Fs):
     return torch.from_numpy(np.ascontiguousarray(arr)).to("cuda:0")
 
 
-def _gpu_solve(space, At, Mt, Fs, precision, fwd_fp64=True, max_refine=30, rtol=SOLVE_RTOL):
-    prob = stfd.Problem(space, At, Mt, precision=precision, fwd_fp64=fwd_fp64, max_refine=max_refine, rtol=rtol)
+def _gpu_solve(space, At, Mt, Fs, precision, fp64_transforms=5, max_refine=30, rtol=SOLVE_RTOL):
+    prob = stfd.Problem(space, At, Mt, precision=precision, fp64_transforms=fp64_transforms, max_refine=max_refine,
+                        rtol=rtol)
     prob.factor()
     F = _to_dev(Fs)
     U = torch.empty_like(F)
@@ -99,6 +100,21 @@ def test_ragged_shapes(precision, nc, t, nrhs):
     Us, rep, prob = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, precision)
     if len(t) - 1 == 7:
         assert prob.setup_report["n_real"] >= 1
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ncx,ncy,nrhs", [(101, 4, 2), (131, 3, 1), (250, 3, 17)],
+                         ids=["band101", "band131", "band250_rhs17"])
+def test_wide_bands(precision, ncx, ncy, nrhs):
+    """Thin rectangles: half-bandwidth ncx (padded to 112, 144, 256), which
+    exercises the wide-band kernel configurations at small M_x."""
+    mesh = w.rect_mesh(ncx, ncy)
+    t = w.uniform_times(12)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[6000 + r for r in range(nrhs)])
+    sp = stfd.Space(mesh)
+    assert sp.half_band == ncx
+    Us, rep, _ = _gpu_solve(sp, At, Mt, Fs, precision)
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 
@@ -151,7 +167,17 @@ def test_fp32_forward_variant_still_converges():
     mesh = w.square_mesh(12)
     t = w.uniform_times(32)
     At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random")
-    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, "fp32", fwd_fp64=False, max_refine=40)
+    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, "fp32", fp64_transforms=0, max_refine=40)
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+@pytest.mark.parametrize("mask", [1, 3, 7])
+def test_fp64_transform_variants(mask):
+    """The FP32 form with other transform GEMMs on FP64 matrix cores."""
+    mesh = w.square_mesh(12)
+    t = w.graded_times(24)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[11, 12])
+    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, "fp32", fp64_transforms=mask)
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 

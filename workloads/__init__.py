@@ -109,6 +109,16 @@ def square_mesh(nc: int) -> Mesh:
     return _grid_mesh(nc, 0.0, 1.0, lambda i, j: True)
 
 
+def rect_mesh(ncx: int, ncy: int) -> Mesh:
+    """Rectangle (0, ncx/ncy) x (0, 1) with ncx x ncy square cells: a wide
+    band (ncx interior nodes per row) at a small number of unknowns."""
+    if ncx < 2 or ncy < 2:
+        raise ValueError("need at least 2 cells per side")
+    h = 1.0 / ncy
+    m = _grid_mesh(max(ncx, ncy), 0.0, max(ncx, ncy) * h, lambda i, j: i < ncx and j < ncy)
+    return Mesh(xy=m.xy, tri=m.tri, dof=m.dof, h=h, rows=m.rows, box=(0.0, ncx * h, 0.0, 1.0))
+
+
 def lshape_mesh(nc: int) -> Mesh:
     """L-shape (-1,1)^2 minus [0,1]x[-1,0]; nc even cells per side, h = 2/nc.
 
