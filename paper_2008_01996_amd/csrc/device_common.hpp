@@ -96,6 +96,25 @@ __device__ __forceinline__ T group_bcast(T v, int k, int grp) {
     return r;
 }
 
+// acc += a * b for complex values given as real pairs, in fused multiply-adds
+template <typename T>
+__device__ __forceinline__ void cmac(T& accr, T& acci, T ar, T ai, T br, T bi) {
+    accr = fma(ar, br, accr);
+    accr = fma(-ai, bi, accr);
+    acci = fma(ar, bi, acci);
+    acci = fma(ai, br, acci);
+}
+
+// Orders one wave's LDS accesses across its lanes for the compiler (values a
+// lane stores are read by other lanes of the same wave afterwards).  The
+// hardware runs the LDS instructions of a wave in issue order, so no wait or
+// workgroup barrier is needed.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // block-wide sum of one double per thread (blockDim.x a multiple of 64, <= 1024)
 __device__ __forceinline__ double block_sum(double v, double* scratch) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
