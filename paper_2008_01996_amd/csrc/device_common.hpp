@@ -15,7 +15,7 @@
 namespace stfd {
 
 template <typename T>
-struct cplx {
+struct alignas(2 * sizeof(T)) cplx {
     T re, im;
 };
 

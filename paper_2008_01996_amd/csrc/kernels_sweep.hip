@@ -45,12 +45,15 @@ template <typename T, int CB, int BPC>
 struct Cfg {
     static constexpr int EL = (CB * (BPC + 1) + NL - 1) / NL;  // L entries per loader lane
     static constexpr int ER = (CB * NRS + NL - 1) / NL;         // right-hand-side values per loader lane
-    static constexpr int EPB = EL * NL + CB;                    // L entries of a slot, columns at stride bp + 2
+    static constexpr int EPB = EL * NL + CB + 1;                // complex L entries of a slot, columns at stride bp + 2
+    static constexpr int ZERO = EPB - 1;                        // a zero entry, never written by the loaders
     static constexpr int ERB = ER * NL;                         // right-hand-side values of a slot
-    static constexpr int SLOT = 2 * EPB + 2 * ERB;              // T elements per slot
+    static constexpr int SLOT = 2 * EPB + 2 * ERB;              // T elements per slot: L (re, im interleaved),
+                                                                // then right-hand-side re, im
 };
 
 // LDS carve-up: [NSLOT slots][ring re][ring im][2 x block buffer re][im][block buffer re][im]
+// (masked L reads below read the slot's zero entry instead of branching)
 template <typename T, int CB, int BPC>
 __host__ __device__ constexpr size_t smem_elems(int bp) {
     return (size_t)NSLOT * Cfg<T, CB, BPC>::SLOT + 2 * (size_t)(bp + CB) * NRS + 6 * (size_t)CB * NRS;
@@ -101,15 +104,11 @@ __device__ __forceinline__ void lds_offsets(int (&off)[EL], int bp1, int li) {
 template <typename T, int EPB, int ERB, int EL, int ER>
 __device__ __forceinline__ void deposit(const cplx<T> (&l)[EL], const cplx<T> (&r)[ER], const int (&off)[EL],
                                         T* slot, int li) {
-    T* LR = slot;
-    T* LI = slot + EPB;
+    cplx<T>* L = reinterpret_cast<cplx<T>*>(slot);
     T* GR = slot + 2 * EPB;
     T* GI = GR + ERB;
 #pragma unroll
-    for (int j = 0; j < EL; ++j) {
-        LR[off[j]] = l[j].re;
-        LI[off[j]] = l[j].im;
-    }
+    for (int j = 0; j < EL; ++j) L[off[j]] = l[j];
 #pragma unroll
     for (int j = 0; j < ER; ++j) {
         GR[li + NL * j] = r[j].re;
@@ -119,29 +118,41 @@ __device__ __forceinline__ void deposit(const cplx<T> (&l)[EL], const cplx<T> (&
 
 // Forward, off the critical path (waves 1-3): rows c0 + CB + rr, rr in
 // [CB, bp), of the pending ring take the update by block (c0, nb) with its
-// solution y.  cs = (c0 + CB) mod ring.
-template <typename T, int CB>
-__device__ __forceinline__ void forward_far_update(const T* LR, const T* LI, const T* YR, const T* YI, T* QR, T* QI,
-                                                   int c0, int nb, int Mx, int bp, int ls, int nr, int cs, int ring,
+// solution y.  cs = (c0 + CB) mod ring.  With PW = 2 the CB columns of a row
+// are split over the two halves of a wave (lane and lane + 32).
+template <typename T, int CB, int PW>
+__device__ __forceinline__ void forward_far_update(const cplx<T>* L, const T* YR, const T* YI, T* QR, T* QI, int c0,
+                                                   int nb, int Mx, int bp, int ls, int nr, int cs, int ring, int zero,
                                                    int li) {
+    constexpr int KP = CB / PW;                   // columns per lane
+    constexpr int IPP = NL / PW;                  // rows per pass
+    const int part = PW == 1 ? 0 : (li & 63) >> 5;
+    const int slot_item = PW == 1 ? li : (li >> 6) * 32 + (li & 31);
     const int nrow = bp - CB;
     for (int t = 0; t < nr; ++t) {
-        for (int m = li; m < nrow; m += NL) {
+        for (int m0 = 0; m0 < nrow; m0 += IPP) {
+            const int m = m0 + slot_item;
             const int rr = CB + m;
-            if (c0 + CB + rr >= Mx) break;
-            const int kmin = CB + rr - bp;   // L[row, c0 + k] lies in the band for k >= kmin
+            const bool row_ok = m < nrow && c0 + CB + rr < Mx;
+            const int kmin = CB + rr - bp;        // L[row, c0 + k] lies in the band for k >= kmin
             T ar = 0, ai = 0;
 #pragma unroll
-            for (int k = 0; k < CB; ++k) {
-                const int d = min(CB + rr - k, bp);
-                const bool on = k < nb && k >= kmin;
-                const T yr = on ? YR[k * NRS + t] : T(0), yi = on ? YI[k * NRS + t] : T(0);
-                cmac(ar, ai, LR[k * ls + d], LI[k * ls + d], yr, yi);
+            for (int kk = 0; kk < KP; ++kk) {
+                const int k = part * KP + kk;
+                const int e = row_ok && k < nb && k >= kmin ? k * ls + CB + rr - k : zero;
+                const cplx<T> l = L[e];
+                cmac(ar, ai, l.re, l.im, YR[k * NRS + t], YI[k * NRS + t]);
             }
-            int s = cs + rr;
-            s = s >= ring ? s - ring : s;
-            QR[s * NRS + t] -= ar;
-            QI[s * NRS + t] -= ai;
+            if constexpr (PW == 2) {
+                ar += __shfl_xor(ar, 32, 64);
+                ai += __shfl_xor(ai, 32, 64);
+            }
+            if (row_ok && part == 0) {
+                int s = cs + rr;
+                s = s >= ring ? s - ring : s;
+                QR[s * NRS + t] -= ar;
+                QI[s * NRS + t] -= ai;
+            }
         }
     }
 }
@@ -150,7 +161,7 @@ __device__ __forceinline__ void forward_far_update(const T* LR, const T* LI, con
 // S[k][t] = sum over rows r in [c0 + 2 CB, min(c0 + k + bp, M_x)) of
 // L[r, c0 + k] z[r][t].  cs = (c0 + CB) mod ring.
 template <typename T, int CB>
-__device__ __forceinline__ void backward_far_sums(const T* LR, const T* LI, const T* ZR, const T* ZI, T* SR, T* SI,
+__device__ __forceinline__ void backward_far_sums(const cplx<T>* L, const T* ZR, const T* ZI, T* SR, T* SI,
                                                   int c0, int Mx, int bp, int ls, int nr, int cs, int ring, int li) {
     const int items = CB * nr;
     int lpw = 0;                                  // 2^lpw lanes share one (k, t) sum
@@ -164,8 +175,10 @@ __device__ __forceinline__ void backward_far_sums(const T* LR, const T* LI, cons
             const int dmax = min(bp, Mx - 1 - c0 - k);
             int s = cs + CB + part;               // ring slot of row c0 + k + d, d = 2 CB - k + part
             s = s >= ring ? s - ring : s;
+#pragma unroll 4
             for (int d = 2 * CB - k + part; d <= dmax; d += pw) {
-                cmac(ar, ai, LR[k * ls + d], LI[k * ls + d], ZR[s * NRS + t], ZI[s * NRS + t]);
+                const cplx<T> l = L[k * ls + d];
+                cmac(ar, ai, l.re, l.im, ZR[s * NRS + t], ZI[s * NRS + t]);
                 s += pw;
                 s = s >= ring ? s - ring : s;
             }
@@ -181,6 +194,52 @@ __device__ __forceinline__ void backward_far_sums(const T* LR, const T* LI, cons
     }
 }
 
+// Broadcast of lane k of this lane's group of CB lanes (G groups; G = 1:
+// lane k of the wave).
+template <typename T, int CB, int G>
+__device__ __forceinline__ T bcast(T v, int k, int grp) {
+    if constexpr (G == 1)
+        return lane_bcast(v, k);
+    else
+        return group_bcast<CB>(v, k, grp);
+}
+
+// Chain over the CB rows of a diagonal block (ascending for the forward
+// sweep, descending for the backward one): v -= l[k] * v_k, with v_k
+// broadcast from lane k of the group once it is final.  A lane whose l[k]
+// are zero for the rows not yet final solves its row; a lane with v = 0
+// that holds other entries of L collects -sum_k l[k] v_k.
+template <typename T, int CB, int G, bool DESC>
+__device__ __forceinline__ void chain(T& vr, T& vi, const cplx<T> (&l)[CB], int grp) {
+#pragma unroll
+    for (int kk = 0; kk < CB; ++kk) {
+        const int k = DESC ? CB - 1 - kk : kk;
+        const T yr = bcast<T, CB, G>(vr, k, grp);
+        const T yi = bcast<T, CB, G>(vi, k, grp);
+        vr = fma(-l[k].re, yr, vr);
+        vr = fma(l[k].im, yi, vr);
+        vi = fma(-l[k].re, yi, vi);
+        vi = fma(-l[k].im, yr, vi);
+    }
+}
+
+// The same chain, also collecting a += sum_k p[k] v_k in the same lane.
+template <typename T, int CB, int G, bool DESC>
+__device__ __forceinline__ void chain2(T& vr, T& vi, T& ar, T& ai, const cplx<T> (&l)[CB], const cplx<T> (&p)[CB],
+                                       int grp) {
+#pragma unroll
+    for (int kk = 0; kk < CB; ++kk) {
+        const int k = DESC ? CB - 1 - kk : kk;
+        const T yr = bcast<T, CB, G>(vr, k, grp);
+        const T yi = bcast<T, CB, G>(vi, k, grp);
+        vr = fma(-l[k].re, yr, vr);
+        vr = fma(l[k].im, yi, vr);
+        vi = fma(-l[k].re, yi, vi);
+        vi = fma(-l[k].im, yr, vi);
+        cmac(ar, ai, p[k].re, p[k].im, yr, yi);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -189,7 +248,6 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                                                            int nrhs, const T* __restrict__ G, T* __restrict__ W) {
     using C = Cfg<T, CB, BPC>;
     constexpr int GPW = 64 / CB;                  // right-hand sides per chain pass
-    constexpr int KPER = CB / GPW;                // columns per lane in the next-block update
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
     const int ls = bp + 2;                        // LDS column stride of L
@@ -232,6 +290,8 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         PI[q] = 0;
     }
 
+    for (int q = tid; q < NSLOT; q += NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
+
     if (wave > 0) {
         // The payload of block b is its L block and the g of the rows
         // b*CB + ring + [0, CB) that enter the window after it.  Register set
@@ -263,8 +323,14 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                 if (i >= 0 && i < nblk) {
                     const T* LR = slots + (i % NSLOT) * C::SLOT;
                     const int yo = (i & 1) * CB * NRS;
-                    forward_far_update<T, CB>(LR, LR + C::EPB, YR + yo, YI + yo, QR, QI, i * CB,
-                                              min(CB, Mx - i * CB), Mx, bp, ls, nr, cs, ring, li);
+                    const cplx<T>* L = reinterpret_cast<const cplx<T>*>(LR);
+                    const int nbi = min(CB, Mx - i * CB);
+                    if ((bp - CB) * nr * 2 <= NL)
+                        forward_far_update<T, CB, 2>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls, nr, cs,
+                                                     ring, C::ZERO, li);
+                    else
+                        forward_far_update<T, CB, 1>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls, nr, cs,
+                                                     ring, C::ZERO, li);
                 }
                 __syncthreads();
                 cs = wrap(cs + CB);
@@ -276,82 +342,77 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
 
     // wave 0: the critical path
     const int k2 = lane % CB, grp = lane / CB;
+    constexpr int ZERO = C::ZERO;
     int cs = 0;
     for (int s = 0; s < nbar; ++s) {
         if (s < nblk) {
-            const T* LR = slots + (s % NSLOT) * C::SLOT;
-            const T* LI = LR + C::EPB;
-            const T* SGR = LR + 2 * C::EPB;
+            const T* slot = slots + (s % NSLOT) * C::SLOT;
+            const cplx<T>* L = reinterpret_cast<const cplx<T>*>(slot);
+            const T* SGR = slot + 2 * C::EPB;
             const T* SGI = SGR + C::ERB;
             T* YRs = YR + (s & 1) * CB * NRS;
             T* YIs = YI + (s & 1) * CB * NRS;
             const int c0 = s * CB;
             const int nb = min(CB, Mx - c0);
-            // row k2 of the unit lower-triangular diagonal block, and D
-            T lr[CB], lim[CB];
-#pragma unroll
-            for (int k = 0; k < CB; ++k) {
-                const bool on = k < k2 && k2 - k <= bp && k < nb;
-                const int d = min(max(k2 - k, 0), bp);
-                lr[k] = on ? LR[k * ls + d] : T(0);
-                lim[k] = on ? LI[k * ls + d] : T(0);
-            }
-            const cplx<T> dinv = cinv(cplx<T>{LR[k2 * ls], LI[k2 * ls]});
+            const cplx<T> dinv = cinv(L[k2 * ls]);
             const int qs = wrap(cs + k2) * NRS;
-            for (int t0 = 0; t0 < nr; t0 += GPW) {
-                const int t = t0 + grp;
-                const int tt = min(t, nr - 1);
-                T vr = QR[qs + tt] - PR[k2 * NRS + tt];
-                T vi = QI[qs + tt] - PI[k2 * NRS + tt];
+            auto put_y = [&](int t, T vr, T vi) {
+                YRs[k2 * NRS + t] = vr;
+                YIs[k2 * NRS + t] = vi;
+                if (k2 < nb) {
+                    const cplx<T> w = cmul(cplx<T>{vr, vi}, dinv);
+                    wre[(size_t)t * rstride + c0 + k2] = w.re;
+                    wim[(size_t)t * rstride + c0 + k2] = w.im;
+                }
+            };
+            if (nr == 1) {
+                // group 0: row k2 of the unit lower-triangular diagonal block;
+                // group 1: row k2 of the block below (collects -P)
+                cplx<T> l[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
-                    const T yr = group_bcast<CB>(vr, k, grp);
-                    const T yi = group_bcast<CB>(vi, k, grp);
-                    T nr_ = 0, ni_ = 0;
-                    cmac(nr_, ni_, lr[k], lim[k], yr, yi);
-                    vr -= nr_;
-                    vi -= ni_;
+                    const int dd = grp * CB + k2 - k;
+                    l[k] = L[grp < 2 && dd > 0 && dd <= bp && k < nb ? k * ls + dd : ZERO];
                 }
-                if (t < nr) {
-                    YRs[k2 * NRS + t] = vr;
-                    YIs[k2 * NRS + t] = vi;
-                    if (k2 < nb) {
-                        const cplx<T> w = cmul(cplx<T>{vr, vi}, dinv);
-                        wre[(size_t)t * rstride + c0 + k2] = w.re;
-                        wim[(size_t)t * rstride + c0 + k2] = w.im;
+                T vr = 0, vi = 0;
+                if (grp == 0) {
+                    vr = QR[qs] - PR[k2 * NRS];
+                    vi = QI[qs] - PI[k2 * NRS];
+                }
+                chain<T, CB, 1, false>(vr, vi, l, grp);
+                wave_lds_sync();
+                if (grp == 0) put_y(0, vr, vi);
+                if (grp == 1) {
+                    PR[k2 * NRS] = -vr;
+                    PI[k2 * NRS] = -vi;
+                }
+            } else {
+                cplx<T> l[CB], p[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    const int da = k2 - k, db = CB + k2 - k;
+                    l[k] = L[da > 0 && da <= bp && k < nb ? k * ls + da : ZERO];
+                    p[k] = L[db <= bp && k < nb ? k * ls + db : ZERO];
+                }
+                for (int t0 = 0; t0 < nr; t0 += GPW) {
+                    const int t = t0 + grp;
+                    const int tt = min(t, nr - 1);
+                    T vr = QR[qs + tt] - PR[k2 * NRS + tt], vi = QI[qs + tt] - PI[k2 * NRS + tt];
+                    T ar = 0, ai = 0;
+                    chain2<T, CB, GPW, false>(vr, vi, ar, ai, l, p, grp);
+                    if (t < nr) {
+                        put_y(t, vr, vi);
+                        PR[k2 * NRS + t] = ar;
+                        PI[k2 * NRS + t] = ai;
                     }
                 }
             }
             wave_lds_sync();
-            // update of the next block's rows: P[j][t] = sum_k L[c0 + CB + j, c0 + k] y_k
-            {
-                const int j = lane % CB, part = lane / CB;
-                for (int t = 0; t < nr; ++t) {
-                    T ar = 0, ai = 0;
-#pragma unroll
-                    for (int kk = 0; kk < KPER; ++kk) {
-                        const int k = part * KPER + kk;
-                        const int dd = CB + j - k;
-                        const bool on = k < nb && dd <= bp;
-                        const int d = min(dd, bp);
-                        const T yr = on ? YRs[k * NRS + t] : T(0), yi = on ? YIs[k * NRS + t] : T(0);
-                        cmac(ar, ai, LR[k * ls + d], LI[k * ls + d], yr, yi);
-                    }
-                    for (int off = CB; off < 64; off <<= 1) {
-                        ar += __shfl_xor(ar, off, 64);
-                        ai += __shfl_xor(ai, off, 64);
-                    }
-                    if (part == 0) {
-                        PR[j * NRS + t] = ar;
-                        PI[j * NRS + t] = ai;
-                    }
-                }
-            }
             // rows entering the window take the slots of the block's rows
             for (int q = lane; q < CB * NRS; q += 64) {
-                const int slot = wrap(cs + q / NRS) * NRS + q % NRS;
-                QR[slot] = SGR[q];
-                QI[slot] = SGI[q];
+                const int sl = wrap(cs + q / NRS) * NRS + q % NRS;
+                QR[sl] = SGR[q];
+                QI[sl] = SGI[q];
             }
         }
         __syncthreads();
@@ -365,7 +426,6 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                                                             int nsys, int nrhs, T* __restrict__ W) {
     using C = Cfg<T, CB, BPC>;
     constexpr int GPW = 64 / CB;
-    constexpr int KPER = CB / GPW;                // rows per lane in the sums over the next block
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
     const int ls = bp + 2;                        // LDS column stride of L
@@ -373,8 +433,10 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
     T* slots = reinterpret_cast<T*>(smem_raw);
     T* ZR = slots + NSLOT * C::SLOT;              // finished z, ring [ring][NRS]
     T* ZI = ZR + ring * NRS;
-    T* SR = ZI + ring * NRS;                      // off-block sums, [2][CB][NRS] by step parity
+    T* SR = ZI + ring * NRS;                      // far sums, [2][CB][NRS] by step parity
     T* SI = SR + 2 * CB * NRS;
+    T* BR = SI + 2 * CB * NRS;                    // sums over the block just finished, [CB][NRS]
+    T* BI = BR + CB * NRS;
     const int sys = blockIdx.x;
     const int r0 = blockIdx.y * NRS;
     const int nr = min(NRS, nrhs - r0);
@@ -396,7 +458,13 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
         SR[q] = 0;
         SI[q] = 0;
     }
+    for (int q = tid; q < CB * NRS; q += NT) {
+        BR[q] = 0;
+        BI[q] = 0;
+    }
     const int cs0 = ((nblk - 1) * CB) % ring;     // c0 of the first block processed, mod ring
+
+    for (int q = tid; q < NSLOT; q += NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
 
     if (wave > 0) {
         // step s processes block nblk - 1 - s; the payload of a block is its L
@@ -433,7 +501,8 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                 if (a >= 0) {
                     const T* LR = slots + ((s + 1) % NSLOT) * C::SLOT;
                     const int so = ((s + 1) & 1) * CB * NRS;
-                    backward_far_sums<T, CB>(LR, LR + C::EPB, ZR, ZI, SR + so, SI + so, a * CB, Mx, bp, ls, nr, cs,
+                    backward_far_sums<T, CB>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so, SI + so, a * CB, Mx,
+                                             bp, ls, nr, cs,
                                              ring, li);
                 }
                 __syncthreads();
@@ -446,77 +515,75 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
 
     // wave 0: the critical path
     const int kp = lane % CB, grp = lane / CB;
+    constexpr int ZERO = C::ZERO;
     int cs = cs0;
     for (int s = 0; s < nbar; ++s) {
         if (s < nblk) {
             const int blk = nblk - 1 - s;
-            const T* LR = slots + (s % NSLOT) * C::SLOT;
-            const T* LI = LR + C::EPB;
-            const T* SWR = LR + 2 * C::EPB;
+            const T* slot = slots + (s % NSLOT) * C::SLOT;
+            const cplx<T>* L = reinterpret_cast<const cplx<T>*>(slot);
+            // block blk - 1, deposited a step ago
+            const cplx<T>* LN = reinterpret_cast<const cplx<T>*>(slots + ((s + 1) % NSLOT) * C::SLOT);
+            const T* SWR = slot + 2 * C::EPB;
             const T* SWI = SWR + C::ERB;
-            T* SRs = SR + (s & 1) * CB * NRS;
-            T* SIs = SI + (s & 1) * CB * NRS;
+            const T* SRs = SR + (s & 1) * CB * NRS;
+            const T* SIs = SI + (s & 1) * CB * NRS;
             const int c0 = blk * CB;
             const int nb = min(CB, Mx - c0);
-            // sums over the rows of the block below (finished in the previous step)
-            {
-                const int part = lane / CB;
-                for (int t = 0; t < nr; ++t) {
-                    T ar = 0, ai = 0;
-#pragma unroll
-                    for (int jj = 0; jj < KPER; ++jj) {
-                        const int j = part * KPER + jj;
-                        const int dd = CB + j - kp;
-                        const bool on = kp < nb && dd <= bp && c0 + CB + j < Mx;
-                        const int d = min(dd, bp);
-                        const int slot = wrap(cs + CB + j) * NRS + t;
-                        const T zr = on ? ZR[slot] : T(0), zi = on ? ZI[slot] : T(0);
-                        cmac(ar, ai, LR[kp * ls + d], LI[kp * ls + d], zr, zi);
-                    }
-                    for (int off = CB; off < 64; off <<= 1) {
-                        ar += __shfl_xor(ar, off, 64);
-                        ai += __shfl_xor(ai, off, 64);
-                    }
-                    if (part == 0) {
-                        SRs[kp * NRS + t] += ar;
-                        SIs[kp * NRS + t] += ai;
-                    }
-                }
-            }
-            // column kp of the diagonal block (entries L[c0 + k, c0 + kp], k > kp)
-            T lr[CB], lim[CB];
-#pragma unroll
-            for (int k = 0; k < CB; ++k) {
-                const bool on = k > kp && k - kp <= bp && k < nb;
-                const int d = min(max(k - kp, 0), bp);
-                lr[k] = on ? LR[kp * ls + d] : T(0);
-                lim[k] = on ? LI[kp * ls + d] : T(0);
-            }
-            wave_lds_sync();
             const int zs = wrap(cs + kp) * NRS;
-            for (int t0 = 0; t0 < nr; t0 += GPW) {
-                const int t = t0 + grp;
-                const bool live = kp < nb && t < nr;
-                const int tt = min(t, nr - 1);
-                T vr = SWR[kp * NRS + tt] - SRs[kp * NRS + tt];
-                T vi = SWI[kp * NRS + tt] - SIs[kp * NRS + tt];
-#pragma unroll
-                for (int kk = 0; kk < CB; ++kk) {
-                    const int k = CB - 1 - kk;
-                    const T zr = group_bcast<CB>(vr, k, grp);
-                    const T zi = group_bcast<CB>(vi, k, grp);
-                    T nr_ = 0, ni_ = 0;
-                    cmac(nr_, ni_, lr[k], lim[k], zr, zi);
-                    vr -= nr_;
-                    vi -= ni_;
-                }
-                if (t < NRS) {
-                    ZR[zs + t] = live ? vr : T(0);
-                    ZI[zs + t] = live ? vi : T(0);
-                }
+            auto put_z = [&](int t, bool live, T vr, T vi) {
+                ZR[zs + t] = live ? vr : T(0);
+                ZI[zs + t] = live ? vi : T(0);
                 if (live) {
                     wre[(size_t)t * rstride + c0 + kp] = vr;
                     wim[(size_t)t * rstride + c0 + kp] = vi;
+                }
+            };
+            if (nr == 1) {
+                // group 0: column kp of the diagonal block (rows c0 + k);
+                // group 1: column kp of the block to the left (collects -B)
+                const cplx<T>* src = grp == 0 ? L : LN;
+                cplx<T> l[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    const int dd = grp * CB + k - kp;
+                    const bool on = grp < 2 && dd > 0 && dd <= bp && k < nb && (grp == 0 || blk > 0);
+                    l[k] = src[on ? kp * ls + dd : ZERO];
+                }
+                const bool live = kp < nb;
+                T vr = 0, vi = 0;
+                if (grp == 0 && live) {
+                    vr = SWR[kp * NRS] - SRs[kp * NRS] - BR[kp * NRS];
+                    vi = SWI[kp * NRS] - SIs[kp * NRS] - BI[kp * NRS];
+                }
+                chain<T, CB, 1, true>(vr, vi, l, grp);
+                wave_lds_sync();
+                if (grp == 0) put_z(0, live, vr, vi);
+                if (grp == 1) {
+                    BR[kp * NRS] = -vr;
+                    BI[kp * NRS] = -vi;
+                }
+            } else {
+                cplx<T> l[CB], p[CB];
+#pragma unroll
+                for (int k = 0; k < CB; ++k) {
+                    const int da = k - kp, db = CB + k - kp;
+                    l[k] = L[da > 0 && da <= bp && k < nb ? kp * ls + da : ZERO];
+                    p[k] = LN[blk > 0 && db <= bp && k < nb ? kp * ls + db : ZERO];
+                }
+                for (int t0 = 0; t0 < nr; t0 += GPW) {
+                    const int t = t0 + grp;
+                    const bool live = kp < nb && t < nr;
+                    const int tt = min(t, nr - 1);
+                    T vr = live ? SWR[kp * NRS + tt] - SRs[kp * NRS + tt] - BR[kp * NRS + tt] : T(0);
+                    T vi = live ? SWI[kp * NRS + tt] - SIs[kp * NRS + tt] - BI[kp * NRS + tt] : T(0);
+                    T ar = 0, ai = 0;
+                    chain2<T, CB, GPW, true>(vr, vi, ar, ai, l, p, grp);
+                    if (t < NRS) {
+                        put_z(t, live, vr, vi);
+                        BR[kp * NRS + t] = ar;
+                        BI[kp * NRS + t] = ai;
+                    }
                 }
             }
         }
