@@ -33,6 +33,17 @@ __device__ __forceinline__ cplx<T> cinv(cplx<T> a) {
     return {ar / d, -ai / d};
 }
 
+// 1/a from the hardware reciprocal (1 ulp) in FP32; the scaled division in FP64
+template <typename T>
+__device__ __forceinline__ cplx<T> cinv_fast(cplx<T> a) {
+    if constexpr (sizeof(T) == 4) {
+        const float s = __builtin_amdgcn_rcpf(a.re * a.re + a.im * a.im);
+        return {a.re * s, -a.im * s};
+    } else {
+        return cinv(a);
+    }
+}
+
 template <typename T>
 struct vec4;
 template <>

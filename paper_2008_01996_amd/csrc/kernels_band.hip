@@ -206,6 +206,167 @@ __global__ void __launch_bounds__(256) band_ldl_kernel(cplx<T>* __restrict__ LB,
 }
 
 // ---------------------------------------------------------------------------
+// The same factorization with the active window resident in LDS.
+// Panel p0 (16 columns) touches only columns [p0, p0 + bp + 16), so the
+// window of bp + 16 band columns (entries d = 0..bp each, ring-indexed by
+// column mod (bp + 16)) is kept in LDS for the whole factorization: the
+// trailing update reads and writes it there, the columns entering the
+// window are loaded into registers one panel ahead, and each finished panel
+// is written to HBM once.  The panel itself is factored in registers.
+// BPC bounds bp (register prefetch sizing); used where the window fits.
+// ---------------------------------------------------------------------------
+template <typename T, int BPC>
+__global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restrict__ LB, int Mx, int bp,
+                                                              int* __restrict__ flag) {
+    constexpr int EP = (16 * (BPC + 1) + 255) / 256;   // prefetched entries per thread
+    constexpr int RH = (BPC + 63) / 64;                // row halves of a panel column per lane
+    extern __shared__ unsigned char smem_raw[];
+    cplx<T>* Wn = reinterpret_cast<cplx<T>*>(smem_raw); // [ring][bp1], then one zero entry
+    const int bp1 = bp + 1;
+    const int ring = bp + 16;
+    const int ZE = ring * bp1;
+    const int sys = blockIdx.x;
+    cplx<T>* base = LB + (size_t)sys * Mx * bp1;
+    const size_t total = (size_t)Mx * bp1;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int ntile = bp / 16;
+    const int tiles_total = ntile * (ntile + 1) / 2;
+    const cplx<T> zero = {T(0), T(0)};
+
+    // window columns [0, ring)
+    const int wcols = min(ring, Mx);
+    for (int e = tid; e < ring * bp1; e += 256) Wn[e] = e < wcols * bp1 ? base[e] : zero;
+    if (tid == 0) Wn[ZE] = zero;
+    // columns of entry tid + 256 j of a 16-column block (fixed for the whole run)
+    int ecol[EP];
+#pragma unroll
+    for (int j = 0; j < EP; ++j) ecol[j] = (tid + 256 * j) / bp1;
+    // registers: the block of 16 columns that enters the window next
+    cplx<T> pf[EP];
+    auto prefetch = [&](int c0) {
+        const size_t b0 = (size_t)c0 * bp1;
+#pragma unroll
+        for (int j = 0; j < EP; ++j) pf[j] = base[min(b0 + tid + 256 * j, total - 1)];
+    };
+    prefetch(ring);
+    __syncthreads();
+
+    int sp0 = 0;                                        // window slot of column p0
+    for (int p0 = 0; p0 < Mx; p0 += 16) {
+        const int nb = min(16, Mx - p0);
+        cplx<T>* P = Wn + (size_t)sp0 * bp1;            // panel columns, contiguous
+        // ---- factor the panel in registers, without barriers.  A lane holds
+        // one row of the panel (its 16 entries): lanes 0-15 of every wave the
+        // rows of the diagonal block (the same in all waves), lanes 16 .. 16 +
+        // bp/4 - 1 of wave w the rows p0 + 16 + (bp/4) w + (lane - 16) below.
+        // Column k: D_k and the l_jk of the block rows come from lanes k and j
+        // by lane broadcasts; A[i, j] -= a_ik l_jk for j > k.
+        {
+            const int rw = bp >> 2;
+            const bool own = lane < 16 || lane - 16 < rw;
+            const int rrel = lane < 16 ? lane : 16 + rw * wave + (lane - 16);
+            cplx<T> a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int d = rrel - c;
+                a[c] = Wn[own && c < nb && d >= 0 && d <= bp ? (sp0 + c) * bp1 + d : ZE];
+            }
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    const cplx<T> dk = {lane_bcast(a[k].re, k), lane_bcast(a[k].im, k)};
+                    const cplx<T> inv = cinv_fast(dk);
+                    if (tid == 0) {
+                        const T mag = fabs(dk.re) + fabs(dk.im);
+                        if (!(mag > T(0)) || !isfinite(mag)) atomicOr(flag, 1);
+                    }
+                    const cplx<T> aik = a[k];
+                    if (rrel > k) a[k] = cmul(aik, inv);
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) {
+                        const T lr = lane_bcast(a[k].re, j), lim = lane_bcast(a[k].im, j);
+                        a[j].re = fma(-aik.re, lr, a[j].re);
+                        a[j].re = fma(aik.im, lim, a[j].re);
+                        a[j].im = fma(-aik.re, lim, a[j].im);
+                        a[j].im = fma(-aik.im, lr, a[j].im);
+                    }
+                }
+            }
+            const bool writer = own && (lane >= 16 || wave == 0);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int d = rrel - c;
+                if (writer && c < nb && d >= 0 && d <= bp) Wn[(sp0 + c) * bp1 + d] = a[c];
+            }
+        }
+        __syncthreads();
+        // ---- trailing update in LDS on the matrix cores
+        // tile (ti, tj), ti >= tj: rows r0 = p0 + 16 + 16 ti, columns c0 = p0 + 16 + 16 tj
+        cplx<T> dpan[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) dpan[kk] = Wn[4 * kk + lk < nb ? (sp0 + 4 * kk + lk) * bp1 : ZE];
+        for (int t = wave; t < tiles_total; t += 4) {
+            int ti = 0;
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            const int tj = t - ti * (ti + 1) / 2;
+            const int rr0 = 16 + 16 * ti, cc0 = 16 + 16 * tj;   // relative to p0
+            // operands: A = L[c', k], c' = p0 + cc0 + li; B = L[r, k] D[k], r = p0 + rr0 + li
+            cplx<T> av[4], lv[4], cv[4];
+            int ce[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const int oc = cc0 + li - k, orr = rr0 + li - k;
+                av[kk] = Wn[k < nb && oc <= bp ? sp0 * bp1 + k * bp1 + oc : ZE];
+                lv[kk] = Wn[k < nb && orr <= bp ? sp0 * bp1 + k * bp1 + orr : ZE];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                // D[c' = p0 + cc0 + mfma_row(lk, j)][r = p0 + rr0 + li]
+                const int cl = cc0 + mfma_row<T>(lk, j);
+                const int d = rr0 + li - cl;
+                int sl = sp0 + cl;
+                sl = sl >= ring ? sl - ring : sl;
+                ce[j] = d >= 0 && d <= bp ? sl * bp1 + d : -1;
+                cv[j] = Wn[ce[j] >= 0 ? ce[j] : ZE];
+            }
+            typename vec4<T>::type accR = zero4<T>(), accI = zero4<T>();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const cplx<T> b = cmul(lv[kk], dpan[kk]);
+                accR = mfma16x16x4<T>(av[kk].re, b.re, accR);
+                accR = mfma16x16x4<T>(-av[kk].im, b.im, accR);
+                accI = mfma16x16x4<T>(av[kk].re, b.im, accI);
+                accI = mfma16x16x4<T>(av[kk].im, b.re, accI);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (ce[j] >= 0) Wn[ce[j]] = cplx<T>{cv[j].re - accR[j], cv[j].im - accI[j]};
+        }
+        __syncthreads();
+        // ---- finished panel to HBM; the block entering the window takes its slots
+        {
+            cplx<T>* dst = base + (size_t)p0 * bp1;
+            const int ncol_in = Mx - (p0 + ring);          // columns of the entering block that exist
+#pragma unroll
+            for (int j = 0; j < EP; ++j) {
+                const int e = tid + 256 * j;
+                if (e < 16 * bp1) {
+                    if (ecol[j] < nb) dst[e] = P[e];
+                    P[e] = ecol[j] < ncol_in ? pf[j] : zero;
+                }
+            }
+        }
+        prefetch(p0 + ring + 16);
+        __syncthreads();
+        sp0 += 16;
+        sp0 = sp0 >= ring ? sp0 - ring : sp0;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -217,12 +378,28 @@ hipError_t launch_band_init(void* LB, int Mx, int bp, int nsys, const int* rowpt
     return hipGetLastError();
 }
 
+// LDS of the window factorization, and whether it is used for this band
 template <typename T>
-size_t band_ldl_smem(int bp) { return 2 * 16 * (size_t)(bp + 1) * sizeof(T); }
+static size_t window_smem(int bp) { return ((size_t)(bp + 16) * (bp + 1) + 1) * sizeof(cplx<T>); }
+template <typename T>
+static bool use_window(int bp) { return bp <= 128 && window_smem<T>(bp) <= 150 * 1024; }
+
+template <typename T>
+size_t band_ldl_smem(int bp) {
+    return use_window<T>(bp) ? window_smem<T>(bp) : 2 * 16 * (size_t)(bp + 1) * sizeof(T);
+}
 
 template <typename T>
 hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStream_t st) {
     const size_t smem = band_ldl_smem<T>(bp);
+    if (use_window<T>(bp)) {
+        hipError_t e = hipFuncSetAttribute((const void*)band_ldl_window_kernel<T, 128>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((band_ldl_window_kernel<T, 128>), dim3(nsys), dim3(256), smem, st,
+                           static_cast<cplx<T>*>(LB), Mx, bp, flag);
+        return hipGetLastError();
+    }
     hipError_t e = hipFuncSetAttribute((const void*)band_ldl_kernel<T>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
