@@ -38,6 +38,19 @@ RTOL = 1e-10
 # MI355X published peaks
 PEAK = {"fp32_mfma": 157.3, "fp64_mfma": 78.6, "hbm_GBs": 8000.0}
 
+# Transform GEMMs that run in FP64 in the FP32 form (the library default:
+# first forward GEMM and back transform), plus the residual which is FP64.
+FP64_STAGES_IN_FP32_FORM = ("fwd1", "back", "resid")
+
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs (each scaled by the same counter on a device copy of known
+# size), keyed by the SHA-256 of the kernel's source file: a changed source
+# reports traffic as null until the counters are taken again.
+TRAFFIC = {
+    # band_ldl_window_kernel<float, 128>, square128_nt256: FETCH 1041453 KiB x 1.9997 + WRITE 2080913 KiB x 1.0
+    "band_ldl": {"source_sha256": "9fa282b3609e92044b461b36c0bf4c23bd8b4fa276d91bae41079d740c873c21", "bytes_per_launch": 4.2635e9},
+}
+
 WORKLOADS = {
     "square16_nt16": dict(domain="square", nc=16, nt=16, T=1.0, grading="uniform", rhs="manufactured", nrhs=1,
                           desc="unit square h=1/16 (M_x=225), uniform N_t=16, T=1, 1 RHS from u=sin(pi x1)sin(pi x2)t^2"),
@@ -174,6 +187,29 @@ def stage_work(stage, Mx, Nt, b, nsys, nrhs, es):
     return None, None
 
 
+def kernel_source_hash(stage):
+    import hashlib
+
+    src = {"band_ldl": "kernels_band.hip", "sweep_fwd": "kernels_sweep.hip", "sweep_bwd": "kernels_sweep.hip"}.get(stage)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2008_01996_amd", "csrc", src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def calib_copy():
+    """A device-to-device copy of 256 MiB (reads 256 MiB, writes 256 MiB),
+    the reference for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    x = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    del x, y
+
+
 def run_gpu(spec, mesh, t, modes, precision, steps, warmup):
     import torch
 
@@ -214,6 +250,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=DEFAULT, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 256 MiB device copy first (reference kernel for HBM counter runs)")
     ap.add_argument("--cpu-budget", type=float, default=30.0,
                     help="seconds of CPU oracle work; a budget above the full solve time also yields the "
                          "oracle's solution and the GPU error against it")
@@ -233,6 +271,8 @@ def main():
         print(f"# cpu baseline: {cpu['value']:.3e} DOF/s on {cpu['cores']} cores ({cpu['sample']})",
               file=sys.stderr, flush=True)
 
+    if args.calib_copy:
+        calib_copy()
     res = {}
     for prec in ("fp32", "fp64"):
         res[prec] = run_gpu(spec, mesh, t, modes, prec, args.steps, args.warmup)
@@ -251,22 +291,33 @@ def main():
     dom = max(prof, key=lambda k: prof[k][0])
     ms_tot, launches = prof[dom]
     avg_ms = ms_tot / max(launches, 1)
-    kind, units = stage_work(dom, Mx, Nt, b, nsys, nrhs, 8)
+    es = 4  # bytes per real in the FP32 form's band factor and sweeps
+    kind, units = stage_work(dom, Mx, Nt, b, nsys, nrhs, es)
     if kind == "hbm":
         achieved = units / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
     else:
         achieved = units / (avg_ms * 1e-3) / 1e12
-        peak = PEAK["fp64_mfma"] if dom in ("fwd1", "resid") else PEAK["fp32_mfma"]
+        peak = PEAK["fp64_mfma"] if dom in FP64_STAGES_IN_FP32_FORM else PEAK["fp32_mfma"]
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    tr = TRAFFIC.get(dom)
+    roof["traffic"] = tr["bytes_per_launch"] if tr and tr["source_sha256"] == kernel_source_hash(dom) else None
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms
     roof["work_per_launch"] = units
 
     stages = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
               for k, v in prof.items()}
+    # achieved HBM rate of the substitution sweeps (algorithmic bytes: every
+    # factor entry once, the right-hand side read and the result written)
+    sweeps = {}
+    for sname in ("sweep_fwd", "sweep_bwd"):
+        ms, n = prof[sname]
+        _, byts = stage_work(sname, Mx, Nt, b, nsys, nrhs, es)
+        gbs = byts / (ms / max(n, 1) * 1e-3) / 1e9
+        sweeps[sname] = {"avg_launch_ms": ms / max(n, 1), "bytes_per_launch": byts, "achieved_GBs": gbs,
+                         "frac_hbm_peak": gbs / PEAK["hbm_GBs"]}
 
     chk = {}
     if not args.no_cpu_baseline:
@@ -286,11 +337,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c32 (FP32 complex factor/sweeps/transforms) + f64 (first forward GEMM, residual, update)",
+        "dtype": "f32 complex (factor, sweeps, second forward GEMM) + f64 (first forward GEMM, back transform, "
+                 "residual, update)",
         "data": "synthetic",
         "config": {"workload": args.workload, "description": spec["desc"], "M_x": Mx, "N_t": Nt, "nrhs": nrhs,
                    "n_sys": nsys, "half_band": b, "rtol": RTOL},
         "roofline": roof,
+        "sweeps": sweeps,
         "cpu_baseline": cpu,
         "fp64_fd": {"value": v64, "ms_per_step": res["fp64"]["sec"] * 1e3,
                     "iterations": res["fp64"]["reps"][-1]["iterations"],
