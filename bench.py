@@ -48,7 +48,7 @@ FP64_STAGES_IN_FP32_FORM = ("fwd1", "back", "resid")
 # reports traffic as null until the counters are taken again.
 TRAFFIC = {
     # band_ldl_window_kernel<float, 128>, square128_nt256: FETCH 1041453 KiB x 1.9997 + WRITE 2080913 KiB x 1.0
-    "band_ldl": {"source_sha256": "9fa282b3609e92044b461b36c0bf4c23bd8b4fa276d91bae41079d740c873c21", "bytes_per_launch": 4.2635e9},
+    ("square128_nt256", "band_ldl"): {"source_sha256": "9fa282b3609e92044b461b36c0bf4c23bd8b4fa276d91bae41079d740c873c21", "bytes_per_launch": 4.2635e9},
 }
 
 WORKLOADS = {
@@ -210,6 +210,10 @@ def calib_copy():
     del x, y
 
 
+def sec_hint(t0):
+    return time.perf_counter() - t0
+
+
 def run_gpu(spec, mesh, t, modes, precision, steps, warmup):
     import torch
 
@@ -221,9 +225,12 @@ def run_gpu(spec, mesh, t, modes, precision, steps, warmup):
     F = torch.from_numpy(np.ascontiguousarray(Fh)).to("cuda:0")
     U = torch.empty_like(F)
     torch.cuda.synchronize()
+    print(f"# {precision}: host setup (eigendecomposition, SVD) for N_t = {len(t) - 1} ...", file=sys.stderr,
+          flush=True)
     t0 = time.perf_counter()
     prob = stfd.Problem(sp, A, M, precision=precision, rtol=RTOL, max_refine=30)
     setup_s = time.perf_counter() - t0
+    print(f"# {precision}: setup {setup_s:.1f} s; warmup", file=sys.stderr, flush=True)
     for _ in range(warmup):
         prob.factor()
         prob.solve(F, U)
@@ -231,9 +238,11 @@ def run_gpu(spec, mesh, t, modes, precision, steps, warmup):
     prob.profile(True)
     reps = []
     t0 = time.perf_counter()
-    for _ in range(steps):
+    for i in range(steps):
         prob.factor()
         reps.append(prob.solve(F, U))
+        if sec_hint(t0) > 20:
+            print(f"# {precision}: step {i + 1}/{steps}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     sec = (time.perf_counter() - t0) / steps
     prof = prob.profile_read()
@@ -263,6 +272,7 @@ def main():
         sys.exit(2)
     spec = WORKLOADS[args.workload]
     mesh, t, modes = build_inputs(spec)
+    print(f"# workload {args.workload}: {spec['desc']}", file=sys.stderr, flush=True)
 
     cpu = None
     U_oracle = None
@@ -301,7 +311,7 @@ def main():
         peak = PEAK["fp64_mfma"] if dom in FP64_STAGES_IN_FP32_FORM else PEAK["fp32_mfma"]
         roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    tr = TRAFFIC.get(dom)
+    tr = TRAFFIC.get((args.workload, dom))
     roof["traffic"] = tr["bytes_per_launch"] if tr and tr["source_sha256"] == kernel_source_hash(dom) else None
     roof["kernel"] = dom
     roof["avg_launch_ms"] = avg_ms

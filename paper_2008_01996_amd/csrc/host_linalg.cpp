@@ -264,6 +264,9 @@ bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<
 bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
                 std::vector<cd>& V, std::string* err) {
     const double eps = std::numeric_limits<double>::epsilon();
+    // rotation threshold on the cosine between two columns: sqrt(n) eps, the
+    // level the rounding of the column inner products allows
+    const double tol = std::sqrt((double)n) * eps;
     // work column-major for contiguous column access
     std::vector<cd> A((size_t)n * n), W((size_t)n * n, 0.0);
     for (int i = 0; i < n; ++i)
@@ -291,7 +294,7 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
                     ga += std::conj(ap[i]) * aq[i];
                 }
                 const double g = std::abs(ga);
-                if (g == 0.0 || g <= eps * std::sqrt(al * be)) continue;
+                if (g == 0.0 || g <= tol * std::sqrt(al * be)) continue;
                 off = std::max(off, g / std::sqrt(al * be));
                 // D = diag(1, e^{-i phi}) makes the Gram matrix real; then a
                 // real Jacobi rotation diagonalises it
@@ -316,7 +319,7 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
             for (int i = m - 1; i > 1; --i) ring[i] = ring[i - 1];
             ring[1] = last;
         }
-        if (off <= 4 * eps) converged = true;
+        if (off <= tol) converged = true;
     }
     if (!converged) {
         if (err) *err = "Jacobi SVD did not converge";

@@ -302,48 +302,57 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
             }
         }
         __syncthreads();
-        // ---- trailing update in LDS on the matrix cores
-        // tile (ti, tj), ti >= tj: rows r0 = p0 + 16 + 16 ti, columns c0 = p0 + 16 + 16 tj
-        cplx<T> dpan[4];
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) dpan[kk] = Wn[4 * kk + lk < nb ? (sp0 + 4 * kk + lk) * bp1 : ZE];
-        for (int t = wave; t < tiles_total; t += 4) {
-            int ti = 0;
-            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-            const int tj = t - ti * (ti + 1) / 2;
-            const int rr0 = 16 + 16 * ti, cc0 = 16 + 16 * tj;   // relative to p0
-            // operands: A = L[c', k], c' = p0 + cc0 + li; B = L[r, k] D[k], r = p0 + rr0 + li
-            cplx<T> av[4], lv[4], cv[4];
-            int ce[4];
+        // ---- trailing update in LDS on the matrix cores.  The operands of
+        // every tile come from the 8 row blocks below the panel: lane (li, lk)
+        // holds L[p0 + 16 + 16 m + li, p0 + 4 kk + lk] and that value times
+        // D, for all m and kk, in registers.  Tile (ti, tj), ti >= tj, covers
+        // rows p0 + 16 + 16 ti + (0..15) and columns p0 + 16 + 16 tj + (0..15);
+        // tile number ti (ti + 1) / 2 + tj goes to wave (number mod 4).
+        {
+            cplx<T> lo[8][4], ld[8][4];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int k = 4 * kk + lk;
-                const int oc = cc0 + li - k, orr = rr0 + li - k;
-                av[kk] = Wn[k < nb && oc <= bp ? sp0 * bp1 + k * bp1 + oc : ZE];
-                lv[kk] = Wn[k < nb && orr <= bp ? sp0 * bp1 + k * bp1 + orr : ZE];
+                const cplx<T> dk = Wn[k < nb ? (sp0 + k) * bp1 : ZE];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    const int o = 16 + 16 * m + li - k;
+                    lo[m][kk] = Wn[m < ntile && k < nb && o <= bp ? (sp0 + k) * bp1 + o : ZE];
+                    ld[m][kk] = cmul(lo[m][kk], dk);
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                // D[c' = p0 + cc0 + mfma_row(lk, j)][r = p0 + rr0 + li]
-                const int cl = cc0 + mfma_row<T>(lk, j);
-                const int d = rr0 + li - cl;
-                int sl = sp0 + cl;
-                sl = sl >= ring ? sl - ring : sl;
-                ce[j] = d >= 0 && d <= bp ? sl * bp1 + d : -1;
-                cv[j] = Wn[ce[j] >= 0 ? ce[j] : ZE];
-            }
-            typename vec4<T>::type accR = zero4<T>(), accI = zero4<T>();
+            for (int ti = 0; ti < 8; ++ti) {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const cplx<T> b = cmul(lv[kk], dpan[kk]);
-                accR = mfma16x16x4<T>(av[kk].re, b.re, accR);
-                accR = mfma16x16x4<T>(-av[kk].im, b.im, accR);
-                accI = mfma16x16x4<T>(av[kk].re, b.im, accI);
-                accI = mfma16x16x4<T>(av[kk].im, b.re, accI);
-            }
+                for (int tj = 0; tj <= ti; ++tj) {
+                    if (ti < ntile && (ti * (ti + 1) / 2 + tj) % 4 == wave) {
+                        int ce[4];
+                        cplx<T> cv[4];
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
-                if (ce[j] >= 0) Wn[ce[j]] = cplx<T>{cv[j].re - accR[j], cv[j].im - accI[j]};
+                        for (int j = 0; j < 4; ++j) {
+                            // D[c' = p0 + 16 + 16 tj + mfma_row(lk, j)][r = p0 + 16 + 16 ti + li]
+                            const int cl = 16 + 16 * tj + mfma_row<T>(lk, j);
+                            const int d = 16 * (ti - tj) + li - mfma_row<T>(lk, j);
+                            int sl = sp0 + cl;
+                            sl = sl >= ring ? sl - ring : sl;
+                            ce[j] = d >= 0 && d <= bp ? sl * bp1 + d : -1;
+                            cv[j] = Wn[ce[j] >= 0 ? ce[j] : ZE];
+                        }
+                        typename vec4<T>::type accR = zero4<T>(), accI = zero4<T>();
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const cplx<T> a = lo[tj][kk], b = ld[ti][kk];
+                            accR = mfma16x16x4<T>(a.re, b.re, accR);
+                            accR = mfma16x16x4<T>(-a.im, b.im, accR);
+                            accI = mfma16x16x4<T>(a.re, b.im, accI);
+                            accI = mfma16x16x4<T>(a.im, b.re, accI);
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (ce[j] >= 0) Wn[ce[j]] = cplx<T>{cv[j].re - accR[j], cv[j].im - accI[j]};
+                    }
+                }
+            }
         }
         __syncthreads();
         // ---- finished panel to HBM; the block entering the window takes its slots
