@@ -205,6 +205,7 @@ extern "C" int stfd_project_f(const stfd_space* s, int Nt, const double* t, int 
     std::vector<double> gx, gw;
     gauss01(n, gx, gw);
     std::vector<double> sx((size_t)s->ntri * nmodes);
+#pragma omp parallel for schedule(static)
     for (int e = 0; e < s->ntri; ++e) {
         const int* v = &s->tri[3 * (size_t)e];
         const double p0x = s->xy[2 * v[0]], p0y = s->xy[2 * v[0] + 1];
@@ -223,6 +224,7 @@ extern "C" int stfd_project_f(const stfd_space* s, int Nt, const double* t, int 
             sx[(size_t)e * nmodes + q] = acc;     // mean over the triangle
         }
     }
+#pragma omp parallel for schedule(static)
     for (int l = 0; l < Nt; ++l) {
         const double t0 = t[l], t1 = t[l + 1], h = t1 - t0;
         for (int q = 0; q < nmodes; ++q) {
@@ -251,8 +253,9 @@ extern "C" int stfd_project_f(const stfd_space* s, int Nt, const double* t, int 
 extern "C" int stfd_assemble_load(const stfd_space* s, int Nt, const double* Ct, const double* F, double* Ft) {
     if (!s || Nt < 1 || !Ct || !F || !Ft) return fail(STFD_EINVAL, "assemble_load: bad arguments");
     const int Mx = s->Mx, nt = s->ntri;
-    // G = M10 F (Mx x Nt), then Ft = G Ct^T
+    // G = M10 F (Mx x Nt), one time interval per task
     std::vector<double> G((size_t)Mx * Nt, 0.0);
+#pragma omp parallel for schedule(static)
     for (int l = 0; l < Nt; ++l)
         for (int i = 0; i < Mx; ++i) {
             double acc = 0.0;
@@ -260,13 +263,22 @@ extern "C" int stfd_assemble_load(const stfd_space* s, int Nt, const double* Ct,
                 acc += s->val10[e] * F[(size_t)l * nt + s->col10[e]];
             G[(size_t)l * Mx + i] = acc;
         }
-    for (int k = 0; k < Nt; ++k) {
-        double* out = Ft + (size_t)k * Mx;
-        std::fill(out, out + Mx, 0.0);
-        for (int l = 0; l < Nt; ++l) {
-            const double ckl = Ct[(size_t)k * Nt + l];
-            const double* g = &G[(size_t)l * Mx];
-            for (int i = 0; i < Mx; ++i) out[i] += ckl * g[i];
+    // Ft = G Ct^T in blocks of rows (a block of G stays in cache over k)
+    constexpr int RB = 128;
+    const int nblk = (Mx + RB - 1) / RB;
+#pragma omp parallel for schedule(static)
+    for (int bi = 0; bi < nblk; ++bi) {
+        const int i0 = bi * RB, i1 = std::min(Mx, i0 + RB);
+        double acc[RB];
+        for (int k = 0; k < Nt; ++k) {
+            for (int i = 0; i < i1 - i0; ++i) acc[i] = 0.0;
+            for (int l = 0; l < Nt; ++l) {
+                const double ckl = Ct[(size_t)k * Nt + l];
+                const double* g = &G[(size_t)l * Mx + i0];
+                for (int i = 0; i < i1 - i0; ++i) acc[i] += ckl * g[i];
+            }
+            double* out = Ft + (size_t)k * Mx + i0;
+            for (int i = 0; i < i1 - i0; ++i) out[i] = acc[i];
         }
     }
     return STFD_OK;
