@@ -72,6 +72,11 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not found: build it with python -m paper_2008_01996_amd.build")
+        # torch ships its own HIP runtime under the same soname as the one the
+        # library links; loading torch first makes both use that one runtime
+        # (the library loaded first left the library's HIP calls without a device)
+        import torch  # noqa: F401
+
         L = C.CDLL(LIB_PATH)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int)
