@@ -293,6 +293,9 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
                         a[j].im = fma(-aik.im, lr, a[j].im);
                     }
                 }
+                // keep each column's broadcasts next to their uses (bounded
+                // scalar-register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
             const bool writer = own && (lane >= 16 || wave == 0);
 #pragma unroll
@@ -376,6 +379,210 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 }
 
 // ---------------------------------------------------------------------------
+// FP32 with padded half-bandwidth 128: the trailing window in registers.
+// Column block B (columns 16B .. 16B + 15) lies in the trailing window of
+// panels q with q < B <= q + 8; there it sits at position m = B - q - 1 and is
+// owned by wave B mod 4.  Its band rows 16B .. 16B + 127 (row blocks B ..
+// B + 7) are kept as eight 16x16 MFMA accumulator tiles, positions 0-3 in
+// slot 0 and 4-7 in slot 1, and every trailing update accumulates into them
+// directly.  Row block B + 8 of the block is only touched by the block's own
+// panel.  When block q becomes the panel its owner writes its tiles to the
+// LDS panel buffer, moves the block at position 4 down to slot 0 and takes
+// the block entering at position 7 (prefetched into registers a panel ahead)
+// into slot 1.  The panel is factored in registers as in the window kernel,
+// written to HBM once, and its rows give the tile operands.
+// ---------------------------------------------------------------------------
+constexpr int RPS = 17;                                   // panel buffer row stride (complex)
+
+__global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restrict__ LB, int Mx,
+                                                           int* __restrict__ flag) {
+    using T = float;
+    using V4 = vec4<float>::type;
+    constexpr int bp = 128, bp1 = 129, NROW = 144;
+    constexpr int EP = (16 * bp1 + 255) / 256;            // write-out entries per thread
+    __shared__ cplx<T> P[NROW * RPS];                     // panel rows p0 + 0..143, 16 columns
+    const int sys = blockIdx.x;
+    cplx<T>* base = LB + (size_t)sys * Mx * bp1;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int nblk = (Mx + 15) / 16;
+    const cplx<T> zero = {T(0), T(0)};
+
+    // tile ra of column block B, this lane's entry j: row 16B + 16 ra + li,
+    // column 16B + 4 lk + j.  Loads are issued raw (clamped address) and
+    // masked where they are used, so that they stay in flight.
+    auto tile_ok = [&](int B, int ra, int j) {
+        return B < nblk && 16 * B + 4 * lk + j < Mx && 16 * ra + li - 4 * lk - j >= 0;
+    };
+    auto tile_load = [&](int B, cplx<T> (&v)[8][4]) {
+#pragma unroll
+        for (int ra = 0; ra < 8; ++ra)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 16 * B + 4 * lk + j;
+                const int d = 16 * ra + li - 4 * lk - j;
+                v[ra][j] = base[tile_ok(B, ra, j) ? (size_t)c * bp1 + d : 0];
+            }
+    };
+    // row block 8 of column block B: entry (row 128 + tid / 16, column tid % 16)
+    const int r8r = 128 + (tid >> 4), r8c = tid & 15;
+    auto row8_ok = [&](int B) { return B < nblk && 16 * B + r8c < Mx && r8r - r8c <= bp; };
+    auto row8_load = [&](int B) -> cplx<T> {
+        return base[row8_ok(B) ? (size_t)(16 * B + r8c) * bp1 + (r8r - r8c) : 0];
+    };
+
+    V4 accR[2][8], accI[2][8];
+    cplx<T> pf[8][4];
+    {
+        // panel 0 straight into P; blocks 1-8 into the owners' slots
+        for (int e = tid; e < NROW * 16; e += 256) {
+            const int r = e >> 4, c = e & 15, d = r - c;
+            const bool ok = c < Mx && d >= 0 && d <= bp;
+            const cplx<T> x = base[ok ? (size_t)c * bp1 + d : 0];
+            P[r * RPS + c] = ok ? x : zero;
+        }
+        const int b0 = wave == 0 ? 4 : wave;
+#pragma unroll
+        for (int sl = 0; sl < 2; ++sl) {
+            tile_load(b0 + 4 * sl, pf);
+#pragma unroll
+            for (int ra = 0; ra < 8; ++ra)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const bool ok = tile_ok(b0 + 4 * sl, ra, j);
+                    accR[sl][ra][j] = ok ? pf[ra][j].re : T(0);
+                    accI[sl][ra][j] = ok ? pf[ra][j].im : T(0);
+                }
+        }
+    }
+    if (wave == 1) tile_load(9, pf);
+    cplx<T> r8 = row8_load(1);
+    int ecol[EP], erow[EP];
+#pragma unroll
+    for (int j = 0; j < EP; ++j) {
+        const int e = tid + 256 * j;
+        ecol[j] = e / bp1;
+        erow[j] = e - ecol[j] * bp1 + ecol[j];            // panel row of band entry (column, d)
+    }
+    __syncthreads();
+
+    for (int q = 0; q < nblk; ++q) {
+        const int p0 = 16 * q;
+        const int nb = min(16, Mx - p0);
+        if (q > 0) {
+            // ---- hand over: block q from its owner's slot 0 into P; the block
+            // at position 4 moves to slot 0, block q + 8 enters slot 1
+            if (wave == (q & 3)) {
+#pragma unroll
+                for (int ra = 0; ra < 8; ++ra)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        P[(16 * ra + li) * RPS + 4 * lk + j] = cplx<T>{accR[0][ra][j], accI[0][ra][j]};
+#pragma unroll
+                for (int ra = 0; ra < 8; ++ra) {
+                    accR[0][ra] = accR[1][ra];
+                    accI[0][ra] = accI[1][ra];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const bool ok = tile_ok(q + 8, ra, j);
+                        accR[1][ra][j] = ok ? pf[ra][j].re : T(0);
+                        accI[1][ra][j] = ok ? pf[ra][j].im : T(0);
+                    }
+                }
+            }
+            P[r8r * RPS + r8c] = row8_ok(q) ? r8 : zero;
+            // prefetch for panel q + 1
+            if (wave == ((q + 1) & 3)) tile_load(q + 9, pf);
+            r8 = row8_load(q + 1);
+        }
+        __syncthreads();
+        // ---- factor the panel in registers (one row per lane: lanes 0-15 the
+        // diagonal block in every wave, lanes 16-47 of wave w rows 16 + 32 w ..)
+        {
+            const bool own = lane < 48;
+            const int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
+            cplx<T> a[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) a[c] = P[(own ? rrel : 0) * RPS + c];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (k < nb) {
+                    const cplx<T> dk = {lane_bcast(a[k].re, k), lane_bcast(a[k].im, k)};
+                    const cplx<T> inv = cinv_fast(dk);
+                    if (tid == 0) {
+                        const T mag = fabs(dk.re) + fabs(dk.im);
+                        if (!(mag > T(0)) || !isfinite(mag)) atomicOr(flag, 1);
+                    }
+                    const cplx<T> aik = a[k];
+                    if (rrel > k) a[k] = cmul(aik, inv);
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) {
+                        const T lr = lane_bcast(a[k].re, j), lim = lane_bcast(a[k].im, j);
+                        a[j].re = fma(-aik.re, lr, a[j].re);
+                        a[j].re = fma(aik.im, lim, a[j].re);
+                        a[j].im = fma(-aik.re, lim, a[j].im);
+                        a[j].im = fma(-aik.im, lr, a[j].im);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            const bool writer = own && (lane >= 16 || wave == 0);
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (writer && c <= rrel) P[rrel * RPS + c] = a[c];
+        }
+        __syncthreads();
+        // ---- finished panel to HBM
+        {
+            cplx<T>* dst = base + (size_t)p0 * bp1;
+#pragma unroll
+            for (int j = 0; j < EP; ++j) {
+                const int e = tid + 256 * j;
+                if (e < 16 * bp1 && ecol[j] < nb) dst[e] = P[erow[j] * RPS + ecol[j]];
+            }
+        }
+        // ---- trailing update into the owners' accumulator tiles.  Operands:
+        // lo[m][kk] = L[p0 + 16 + 16 m + li, p0 + 4 kk + lk], ld = lo * D.
+        // Tile (row block q + 1 + m + ra, column block q + 1 + m):
+        //   C[c', r] -= sum_k L[c', k] D_k L[r, k].
+        {
+            cplx<T> lo[8][4], ld[8][4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const cplx<T> dk = P[k * RPS + k];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    lo[m][kk] = P[(16 + 16 * m + li) * RPS + k];
+                    ld[m][kk] = cmul(lo[m][kk], dk);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                if (((q + 1 + m) & 3) == wave && q + 1 + m < nblk) {
+#pragma unroll
+                    for (int ra = 0; ra < 8 - m; ++ra) {
+                        V4 cr = accR[m >= 4][ra], ci = accI[m >= 4][ra];
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const cplx<T> x = lo[m][kk], y = ld[m + ra][kk];
+                            cr = mfma16x16x4<T>(-x.re, y.re, cr);
+                            cr = mfma16x16x4<T>(x.im, y.im, cr);
+                            ci = mfma16x16x4<T>(-x.re, y.im, ci);
+                            ci = mfma16x16x4<T>(-x.im, y.re, ci);
+                        }
+                        accR[m >= 4][ra] = cr;
+                        accI[m >= 4][ra] = ci;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -401,6 +608,13 @@ size_t band_ldl_smem(int bp) {
 template <typename T>
 hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStream_t st) {
     const size_t smem = band_ldl_smem<T>(bp);
+    if constexpr (sizeof(T) == 4) {
+        if (bp == 128) {
+            hipLaunchKernelGGL(band_ldl_reg_kernel, dim3(nsys), dim3(256), 0, st, static_cast<cplx<float>*>(LB), Mx,
+                               flag);
+            return hipGetLastError();
+        }
+    }
     if (use_window<T>(bp)) {
         hipError_t e = hipFuncSetAttribute((const void*)band_ldl_window_kernel<T, 128>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);

@@ -104,11 +104,12 @@ def test_ragged_shapes(precision, nc, t, nrhs):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("ncx,ncy,nrhs", [(101, 4, 2), (131, 3, 1), (250, 3, 17)],
-                         ids=["band101", "band131", "band250_rhs17"])
+@pytest.mark.parametrize("ncx,ncy,nrhs", [(101, 4, 2), (128, 3, 1), (120, 6, 9), (131, 3, 1), (250, 3, 17)],
+                         ids=["band101", "band128", "band120_rhs9", "band131", "band250_rhs17"])
 def test_wide_bands(precision, ncx, ncy, nrhs):
-    """Thin rectangles: half-bandwidth ncx (padded to 112, 144, 256), which
-    exercises the wide-band kernel configurations at small M_x."""
+    """Thin rectangles: half-bandwidth ncx (padded to 112, 128, 128, 144,
+    256), which exercises every band-kernel configuration at small M_x
+    (padded 128 in FP32 is the register-resident factorization)."""
     mesh = w.rect_mesh(ncx, ncy)
     t = w.uniform_times(12)
     At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[6000 + r for r in range(nrhs)])
