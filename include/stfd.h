@@ -273,6 +273,34 @@ int stfd_profile_read(stfd_problem* p, double* ms, long long* counts);
 
 void stfd_problem_free(stfd_problem* p);
 
+/* ---------------------------------------------------------------------------
+ * Batches of independent problems of uneven size (many (M_x, N_t) problems,
+ * each with its own right-hand sides), solved by Algorithm FD (Sec. 4.4)
+ * with FP64 refinement as in stfd_fd_solve, in lockstep: every refinement
+ * round queues one FD application and one residual for every problem that
+ * has not converged, then synchronises hip_stream once to read the residual
+ * norms of all of them.
+ *
+ * stfd_batch_create: np problems (each from stfd_fd_setup, distinct, owned
+ *   by the caller and kept alive while the batch is used; the batch only
+ *   refers to them).  Errors: STFD_EINVAL (np < 1, null or repeated problem),
+ *   STFD_ENOMEM.
+ * stfd_batch_factor: stfd_fd_factor for every problem, stream-ordered.
+ * stfd_batch_solve: nrhs[i] right-hand sides for problem i in F_dev[i]
+ *   (device FP64 [rhs][k][i] blocks, read only) -> U_dev[i] (same layout,
+ *   overwritten); reps: np reports (may be NULL).  Each problem stops at its
+ *   own rtol / max_refine.  Returns STFD_OK when every problem converged,
+ *   else the first failure (STFD_ENOCONV, STFD_ENUMERIC, ...); the reports
+ *   say which problem did what.  Errors also: STFD_ESTATE (a problem not
+ *   factored), STFD_EINVAL, STFD_ENOMEM, STFD_EHIP.
+ * stfd_batch_free: frees the batch only, not the problems.
+ * ------------------------------------------------------------------------- */
+int stfd_batch_create(int np, stfd_problem* const* problems, stfd_batch** out);
+int stfd_batch_factor(stfd_batch* b, void* hip_stream);
+int stfd_batch_solve(stfd_batch* b, const int* nrhs, const double* const* F_dev, double* const* U_dev,
+                     stfd_solve_report* reps, void* hip_stream);
+void stfd_batch_free(stfd_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

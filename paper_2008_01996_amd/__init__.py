@@ -3,5 +3,5 @@
 The solver lives in the C library libstfd.so (include/stfd.h); this package
 holds its sources (csrc/), the build script and the ctypes binding.
 """
-from .stfd import (EINVAL, ENOCONV, ENOMEM, ENUMERIC, ESTATE, EHIP, OK, Problem, Space, StfdError,  # noqa: F401
+from .stfd import (EINVAL, ENOCONV, ENOMEM, ENUMERIC, ESTATE, EHIP, OK, Batch, Problem, Space, StfdError,  # noqa: F401
                    assemble_time, lib, time_decompose)

@@ -52,11 +52,12 @@ struct Cfg {
                                                                 // then right-hand-side re, im
 };
 
-// LDS carve-up: [NSLOT slots][ring re][ring im][2 x block buffer re][im][block buffer re][im]
+// LDS carve-up: [NSLOT slots][ring re][ring im][block buffers: forward 2 x Y re/im + P re/im;
+// backward 2 x 3 far-sum partials re/im + B re/im]
 // (masked L reads below read the slot's zero entry instead of branching)
 template <typename T, int CB, int BPC>
 __host__ __device__ constexpr size_t smem_elems(int bp) {
-    return (size_t)NSLOT * Cfg<T, CB, BPC>::SLOT + 2 * (size_t)(bp + CB) * NRS + 6 * (size_t)CB * NRS;
+    return (size_t)NSLOT * Cfg<T, CB, BPC>::SLOT + 2 * (size_t)(bp + CB) * NRS + 14 * (size_t)CB * NRS;
 }
 
 // Loader: global -> registers for block blk.  Addresses are clamped into the
@@ -157,39 +158,36 @@ __device__ __forceinline__ void forward_far_update(const cplx<T>* L, const T* YR
     }
 }
 
-// Backward, off the critical path (waves 1-3): for the full block at c0,
-// S[k][t] = sum over rows r in [c0 + 2 CB, min(c0 + k + bp, M_x)) of
-// L[r, c0 + k] z[r][t].  cs = (c0 + CB) mod ring.
-template <typename T, int CB>
-__device__ __forceinline__ void backward_far_sums(const cplx<T>* L, const T* ZR, const T* ZI, T* SR, T* SI,
-                                                  int c0, int Mx, int bp, int ls, int nr, int cs, int ring, int li) {
-    const int items = CB * nr;
-    int lpw = 0;                                  // 2^lpw lanes share one (k, t) sum
-    while (lpw < 6 && (items << (lpw + 1)) <= NL) ++lpw;
-    const int pw = 1 << lpw;
-    for (int b0 = 0; b0 < items; b0 += NL >> lpw) {
-        const int item = b0 + (li >> lpw), part = li & (pw - 1);
-        const int k = item % CB, t = item / CB;
+// Backward, off the critical path (waves 1-3): for the full block at c0 and
+// every column k, partial sums over rows r = c0 + 2 CB + m (m < bp - CB) of
+// L[r, c0 + k] z[r][t].  Lane li takes column k = li % CB and the RPC rows of
+// chunk li / CB; the chunks of a wave are added by shuffles and loader wave w
+// writes its partial to S[w][k][t].  cs = (c0 + CB) mod ring.
+template <typename T, int CB, int RPC>
+__device__ __forceinline__ void backward_far_sums(const cplx<T>* L, const T* ZR, const T* ZI, T* SR, T* SI, int c0,
+                                                  int Mx, int bp, int ls, int nr, int cs, int ring, int zero,
+                                                  int li) {
+    const int k = li % CB, ch = li / CB, w = li >> 6;
+    const int nrow = bp - CB;
+    for (int t = 0; t < nr; ++t) {
         T ar = 0, ai = 0;
-        if (item < items) {
-            const int dmax = min(bp, Mx - 1 - c0 - k);
-            int s = cs + CB + part;               // ring slot of row c0 + k + d, d = 2 CB - k + part
-            s = s >= ring ? s - ring : s;
-#pragma unroll 4
-            for (int d = 2 * CB - k + part; d <= dmax; d += pw) {
-                const cplx<T> l = L[k * ls + d];
-                cmac(ar, ai, l.re, l.im, ZR[s * NRS + t], ZI[s * NRS + t]);
-                s += pw;
-                s = s >= ring ? s - ring : s;
-            }
+#pragma unroll
+        for (int i = 0; i < RPC; ++i) {
+            const int m = ch * RPC + i;
+            const int d = 2 * CB + m - k;          // r - (c0 + k)
+            const bool on = m < nrow && d <= bp && c0 + 2 * CB + m < Mx;
+            const cplx<T> l = L[on ? k * ls + d : zero];
+            int sl = cs + CB + min(m, max(nrow - 1, 0));
+            sl = sl >= ring ? sl - ring : sl;
+            cmac(ar, ai, l.re, l.im, ZR[sl * NRS + t], ZI[sl * NRS + t]);
         }
-        for (int off = pw >> 1; off > 0; off >>= 1) {
+        for (int off = CB; off < 64; off <<= 1) {
             ar += __shfl_xor(ar, off, 64);
             ai += __shfl_xor(ai, off, 64);
         }
-        if (part == 0 && item < items) {
-            SR[k * NRS + t] = ar;
-            SI[k * NRS + t] = ai;
+        if ((li & 63) < CB) {
+            SR[(w * CB + k) * NRS + t] = ar;
+            SI[(w * CB + k) * NRS + t] = ai;
         }
     }
 }
@@ -433,9 +431,9 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
     T* slots = reinterpret_cast<T*>(smem_raw);
     T* ZR = slots + NSLOT * C::SLOT;              // finished z, ring [ring][NRS]
     T* ZI = ZR + ring * NRS;
-    T* SR = ZI + ring * NRS;                      // far sums, [2][CB][NRS] by step parity
-    T* SI = SR + 2 * CB * NRS;
-    T* BR = SI + 2 * CB * NRS;                    // sums over the block just finished, [CB][NRS]
+    T* SR = ZI + ring * NRS;                      // far-sum partials, [2][3][CB][NRS] by step parity
+    T* SI = SR + 6 * CB * NRS;
+    T* BR = SI + 6 * CB * NRS;                    // sums over the block just finished, [CB][NRS]
     T* BI = BR + CB * NRS;
     const int sys = blockIdx.x;
     const int r0 = blockIdx.y * NRS;
@@ -454,7 +452,7 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
         ZR[q] = 0;
         ZI[q] = 0;
     }
-    for (int q = tid; q < 2 * CB * NRS; q += NT) {
+    for (int q = tid; q < 6 * CB * NRS; q += NT) {
         SR[q] = 0;
         SI[q] = 0;
     }
@@ -500,10 +498,10 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                 const int a = nblk - 2 - s;
                 if (a >= 0) {
                     const T* LR = slots + ((s + 1) % NSLOT) * C::SLOT;
-                    const int so = ((s + 1) & 1) * CB * NRS;
-                    backward_far_sums<T, CB>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so, SI + so, a * CB, Mx,
-                                             bp, ls, nr, cs,
-                                             ring, li);
+                    const int so = ((s + 1) & 1) * 3 * CB * NRS;
+                    constexpr int RPC = (BPC - CB + NL / CB - 1) / (NL / CB);
+                    backward_far_sums<T, CB, RPC>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so, SI + so,
+                                                  a * CB, Mx, bp, ls, nr, cs, ring, C::ZERO, li);
                 }
                 __syncthreads();
                 cs = cs >= CB ? cs - CB : cs - CB + ring;
@@ -526,8 +524,10 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
             const cplx<T>* LN = reinterpret_cast<const cplx<T>*>(slots + ((s + 1) % NSLOT) * C::SLOT);
             const T* SWR = slot + 2 * C::EPB;
             const T* SWI = SWR + C::ERB;
-            const T* SRs = SR + (s & 1) * CB * NRS;
-            const T* SIs = SI + (s & 1) * CB * NRS;
+            const T* SRs = SR + (s & 1) * 3 * CB * NRS;   // far sums: three partials
+            const T* SIs = SI + (s & 1) * 3 * CB * NRS;
+            auto far_r = [&](int q) { return SRs[q] + SRs[CB * NRS + q] + SRs[2 * CB * NRS + q]; };
+            auto far_i = [&](int q) { return SIs[q] + SIs[CB * NRS + q] + SIs[2 * CB * NRS + q]; };
             const int c0 = blk * CB;
             const int nb = min(CB, Mx - c0);
             const int zs = wrap(cs + kp) * NRS;
@@ -553,8 +553,8 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                 const bool live = kp < nb;
                 T vr = 0, vi = 0;
                 if (grp == 0 && live) {
-                    vr = SWR[kp * NRS] - SRs[kp * NRS] - BR[kp * NRS];
-                    vi = SWI[kp * NRS] - SIs[kp * NRS] - BI[kp * NRS];
+                    vr = SWR[kp * NRS] - far_r(kp * NRS) - BR[kp * NRS];
+                    vi = SWI[kp * NRS] - far_i(kp * NRS) - BI[kp * NRS];
                 }
                 chain<T, CB, 1, true>(vr, vi, l, grp);
                 wave_lds_sync();
@@ -575,8 +575,8 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                     const int t = t0 + grp;
                     const bool live = kp < nb && t < nr;
                     const int tt = min(t, nr - 1);
-                    T vr = live ? SWR[kp * NRS + tt] - SRs[kp * NRS + tt] - BR[kp * NRS + tt] : T(0);
-                    T vi = live ? SWI[kp * NRS + tt] - SIs[kp * NRS + tt] - BI[kp * NRS + tt] : T(0);
+                    T vr = live ? SWR[kp * NRS + tt] - far_r(kp * NRS + tt) - BR[kp * NRS + tt] : T(0);
+                    T vi = live ? SWI[kp * NRS + tt] - far_i(kp * NRS + tt) - BI[kp * NRS + tt] : T(0);
                     T ar = 0, ai = 0;
                     chain2<T, CB, GPW, true>(vr, vi, ar, ai, l, p, grp);
                     if (t < NRS) {

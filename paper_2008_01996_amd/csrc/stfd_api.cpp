@@ -700,6 +700,132 @@ extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, dou
     return STFD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// batches: lockstep refinement over independent problems
+// ---------------------------------------------------------------------------
+struct stfd_batch {
+    std::vector<stfd_problem*> probs;
+};
+
+extern "C" int stfd_batch_create(int np, stfd_problem* const* problems, stfd_batch** out) {
+    if (!out || np < 1 || !problems) return fail(STFD_EINVAL, "batch_create: bad arguments");
+    *out = nullptr;
+    std::vector<stfd_problem*> v(problems, problems + np);
+    for (int i = 0; i < np; ++i) {
+        if (!v[i]) return fail(STFD_EINVAL, "batch_create: null problem");
+        for (int j = 0; j < i; ++j)
+            if (v[j] == v[i]) return fail(STFD_EINVAL, "batch_create: repeated problem");
+    }
+    auto* b = new (std::nothrow) stfd_batch();
+    if (!b) return fail(STFD_ENOMEM, "batch_create: out of memory");
+    b->probs = std::move(v);
+    *out = b;
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" int stfd_batch_factor(stfd_batch* b, void* hip_stream) {
+    if (!b) return fail(STFD_EINVAL, "batch_factor: null batch");
+    for (auto* p : b->probs) {
+        const int rc = stfd_fd_factor(p, hip_stream);
+        if (rc) return rc;
+    }
+    return STFD_OK;
+}
+
+extern "C" int stfd_batch_solve(stfd_batch* b, const int* nrhs, const double* const* F_dev, double* const* U_dev,
+                                stfd_solve_report* reps, void* hip_stream) {
+    if (!b || !nrhs || !F_dev || !U_dev) return fail(STFD_EINVAL, "batch_solve: bad arguments");
+    const int np = (int)b->probs.size();
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < np; ++i) {
+        stfd_problem* p = b->probs[i];
+        if (nrhs[i] < 1 || !F_dev[i] || !U_dev[i]) return fail(STFD_EINVAL, "batch_solve: bad problem arguments");
+        if (!p->factored) return fail(STFD_ESTATE, "batch_solve: a problem is not factored");
+        const int rc = ensure_work(p, nrhs[i]);
+        if (rc) return rc;
+    }
+    std::vector<stfd_solve_report> r(np);
+    std::vector<int> status(np, STFD_ENOCONV), active(np, 1), flag(np, 0);
+    std::vector<const double*> X(F_dev, F_dev + np);
+    std::vector<std::vector<double>> norms(np);
+    int max_it = 0;
+    for (int i = 0; i < np; ++i) {
+        stfd_problem* p = b->probs[i];
+        r[i].nrhs = nrhs[i];
+        norms[i].resize(2 * nrhs[i]);
+        max_it = std::max(max_it, p->opts.max_refine);
+        HIPCHK(stfd::launch_fill_zero(U_dev[i], (size_t)p->Mx * p->Nt * nrhs[i], st), "batch: zero U");
+    }
+    for (int it = 0; it <= max_it; ++it) {
+        int n_active = 0;
+        for (int i = 0; i < np; ++i) {
+            if (!active[i]) continue;
+            stfd_problem* p = b->probs[i];
+            int rc = fd_apply(p, nrhs[i], X[i], U_dev[i], st);
+            if (rc) return rc;
+            rc = residual(p, nrhs[i], F_dev[i], U_dev[i], p->d_R, st);
+            if (rc) return rc;
+            HIPCHK(hipMemcpyAsync(norms[i].data(), p->d_norms, 2 * nrhs[i] * sizeof(double), hipMemcpyDeviceToHost,
+                                  st),
+                   "batch: norms copy");
+            if (it == 0) HIPCHK(hipMemcpyAsync(&flag[i], p->d_flag, sizeof(int), hipMemcpyDeviceToHost, st), "flag");
+            ++n_active;
+        }
+        if (!n_active) break;
+        HIPCHK(hipStreamSynchronize(st), "batch_solve: sync");
+        for (int i = 0; i < np; ++i) {
+            if (!active[i]) continue;
+            stfd_problem* p = b->probs[i];
+            if (flag[i]) {
+                status[i] = STFD_ENUMERIC;
+                active[i] = 0;
+                continue;
+            }
+            double rel = 0.0;
+            bool finite = true;
+            for (int q = 0; q < nrhs[i]; ++q) {
+                const double rr = norms[i][2 * q], ff = norms[i][2 * q + 1];
+                if (!std::isfinite(rr)) finite = false;
+                rel = std::max(rel, ff > 0 ? std::sqrt(rr / ff) : std::sqrt(rr));
+            }
+            r[i].rel_residual[it] = rel;
+            r[i].iterations = it + 1;
+            if (!finite) {
+                status[i] = STFD_ENUMERIC;
+                active[i] = 0;
+            } else if (rel <= p->opts.rtol) {
+                status[i] = STFD_OK;
+                r[i].converged = 1;
+                active[i] = 0;
+            } else if (it >= p->opts.max_refine) {
+                active[i] = 0;
+            } else {
+                X[i] = p->d_R;
+            }
+        }
+    }
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int first = STFD_OK;
+    for (int i = 0; i < np; ++i) {
+        stfd_problem* p = b->probs[i];
+        if (p->prof_on) {
+            const int rc = drain_profile(p);
+            if (rc) return rc;
+        }
+        r[i].seconds = sec;
+        if (reps) reps[i] = r[i];
+        if (first == STFD_OK && status[i] != STFD_OK) first = status[i];
+    }
+    if (first == STFD_ENUMERIC) return fail(STFD_ENUMERIC, "batch_solve: zero/non-finite pivot or residual");
+    if (first == STFD_ENOCONV) return fail(STFD_ENOCONV, "batch_solve: rtol not reached within max_refine");
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+extern "C" void stfd_batch_free(stfd_batch* b) { delete b; }
+
 extern "C" int stfd_profile(stfd_problem* p, int enable) {
     if (!p) return fail(STFD_EINVAL, "profile: null problem");
     int rc = drain_profile(p);

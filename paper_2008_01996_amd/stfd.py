@@ -25,7 +25,8 @@ EXPORTED = [
     "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_fd_setup",
     "stfd_fd_setup_report", "stfd_fd_factor", "stfd_fd_solve", "stfd_kh_residual",
     "stfd_problem_free", "stfd_fd_apply", "stfd_spatial_solve", "stfd_system_lambdas",
-    "stfd_profile", "stfd_profile_read",
+    "stfd_profile", "stfd_profile_read", "stfd_batch_create", "stfd_batch_factor", "stfd_batch_solve",
+    "stfd_batch_free",
 ]
 
 STAGES = ["band_init", "band_ldl", "fwd1", "fwd2", "sweep_fwd", "sweep_bwd", "back", "spatial", "resid",
@@ -105,6 +106,11 @@ def lib():
         L.stfd_profile_read.argtypes = [vp, dp, C.POINTER(C.c_longlong)]
         L.stfd_problem_free.argtypes = [vp]
         L.stfd_problem_free.restype = None
+        L.stfd_batch_create.argtypes = [C.c_int, C.POINTER(vp), C.POINTER(vp)]
+        L.stfd_batch_factor.argtypes = [vp, vp]
+        L.stfd_batch_solve.argtypes = [vp, ip, C.POINTER(vp), C.POINTER(vp), C.POINTER(SolveReport), vp]
+        L.stfd_batch_free.argtypes = [vp]
+        L.stfd_batch_free.restype = None
         _LIB = L
     return _LIB
 
@@ -301,3 +307,41 @@ class Problem:
         _check(lib().stfd_kh_residual(self._h, n, C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
                                       C.c_void_p(R.data_ptr()), _dp(norms), C.c_void_p(_stream_ptr(stream))))
         return norms.reshape(n, 2)
+
+
+class Batch:
+    """Independent problems solved together (lockstep refinement, one host
+    synchronisation per round for all of them).  Keeps the problems alive."""
+
+    def __init__(self, problems):
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p._h for p in self.problems])
+        h = C.c_void_p()
+        _check(lib().stfd_batch_create(len(self.problems), arr, C.byref(h)))
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _LIB is not None:
+            _LIB.stfd_batch_free(h)
+            self._h = None
+
+    def factor(self, stream=None):
+        _check(lib().stfd_batch_factor(self._h, C.c_void_p(_stream_ptr(stream))))
+
+    def solve(self, Fs, Us, stream=None, check=True):
+        """Fs, Us: lists of torch float64 CUDA tensors (nrhs_i, N_t_i, M_x_i).
+        Returns (status, list of per-problem report dicts)."""
+        n = len(self.problems)
+        assert len(Fs) == n and len(Us) == n
+        for p, F, U in zip(self.problems, Fs, Us):
+            assert F.is_contiguous() and U.is_contiguous() and F.shape == U.shape
+            assert F.shape[1:] == (p.Nt, p.Mx)
+        nr = (C.c_int * n)(*[F.shape[0] for F in Fs])
+        fp = (C.c_void_p * n)(*[F.data_ptr() for F in Fs])
+        up = (C.c_void_p * n)(*[U.data_ptr() for U in Us])
+        reps = (SolveReport * n)()
+        rc = lib().stfd_batch_solve(self._h, nr, fp, up, reps, C.c_void_p(_stream_ptr(stream)))
+        if check:
+            _check(rc)
+        return rc, [r.as_dict() for r in reps]

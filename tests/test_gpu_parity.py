@@ -129,6 +129,52 @@ def test_lshape_variable_rows(precision):
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_of_uneven_problems(precision):
+    """Three problems of different spatial and time sizes and right-hand-side
+    counts solved as one batch: each matches the oracle, and each is identical
+    to solving it alone (the batch only interleaves the same launches)."""
+    cases = [(w.square_mesh(8), w.uniform_times(8), [4000, 4001]),
+             (w.square_mesh(12), w.graded_times(12), [4008]),
+             (w.lshape_mesh(8), w.paper_times(1), [4016, 4017, 4018])]
+    probs, Fd, Ud, oracle = [], [], [], []
+    for mesh, t, seeds in cases:
+        At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=seeds)
+        p = stfd.Problem(stfd.Space(mesh), At, Mt, precision=precision, max_refine=30, rtol=SOLVE_RTOL)
+        probs.append(p)
+        Fd.append(_to_dev(Fs))
+        Ud.append(torch.empty_like(Fd[-1]))
+        oracle.append((At, Mt, Mx, Ax, Fs))
+    batch = stfd.Batch(probs)
+    batch.factor()
+    rc, reps = batch.solve(Fd, Ud)
+    torch.cuda.synchronize()
+    assert rc == 0
+    for i, (At, Mt, Mx, Ax, Fs) in enumerate(oracle):
+        Us = [u.T.copy() for u in Ud[i].cpu().numpy()]
+        _check(At, Mt, Mx, Ax, Fs, Us, reps[i])
+        # alone
+        U1 = torch.empty_like(Fd[i])
+        rep1 = probs[i].solve(Fd[i], U1)
+        torch.cuda.synchronize()
+        assert rep1["iterations"] == reps[i]["iterations"]
+        assert torch.equal(U1, Ud[i])
+
+
+def test_batch_rejects_bad_input():
+    mesh = w.square_mesh(6)
+    t = w.uniform_times(4)
+    At, Mt, Ct = tm.kernel(t)
+    p = stfd.Problem(stfd.Space(mesh), At, Mt, precision="fp64")
+    with pytest.raises(stfd.StfdError):
+        stfd.Batch([p, p])
+    b = stfd.Batch([p])
+    F = torch.zeros((1, 4, p.Mx), dtype=torch.float64, device="cuda:0")
+    U = torch.empty_like(F)
+    rc, _ = b.solve([F], [U], check=False)
+    assert rc == stfd.ESTATE
+
+
 def test_end_to_end_library_assembly():
     """The library assembles time matrices, spatial matrices and the load
     itself; the result matches the all-oracle solution."""
