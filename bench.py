@@ -61,6 +61,9 @@ WORKLOADS = {
     "lshape128_nt1024": dict(domain="lshape", nc=256, nt=1024, T=1.0, grading="graded", rhs="random", nrhs=16,
                              desc="L-shape h=1/128 (M_x=48641), graded t_i=(i/N_t)^2 N_t=1024, T=1, 16 RHS seeded smooth random f"),
 }
+WORKLOADS["batch96"] = dict(domain="batch", nrhs=8,
+                            desc="96 problems in one batch: unit square h in {1/32, 1/64, 1/128} x uniform N_t in "
+                                 "{32, 128, 512} (problem p in class p mod 9), T=1, 8 seeded smooth random RHS each")
 DEFAULT = "square128_nt256"
 
 
@@ -265,6 +268,111 @@ def run_gpu(loads, t, precision, steps, warmup):
             "setup": prob.setup_report, "Mx": sp.Mx, "b": sp.half_band}
 
 
+def run_batch(steps, warmup, precision):
+    """The batched workload: every problem set up (the time-pencil
+    decomposition is shared by problems with the same time mesh), then per
+    step one batch factorization and one lockstep batch solve."""
+    import torch
+
+    from paper_2008_01996_amd import stfd
+
+    spaces, tmats, probs, Fd, Ud = {}, {}, [], [], []
+    dofs = 0
+    t0 = time.perf_counter()
+    for pidx in range(96):
+        nc, nt = w.batch_problem_class(pidx)
+        if nc not in spaces:
+            spaces[nc] = stfd.Space(w.square_mesh(nc))
+        if nt not in tmats:
+            tmats[nt] = (w.uniform_times(nt),) + tuple(stfd.assemble_time(w.uniform_times(nt)))
+        sp = spaces[nc]
+        t, A, M, C = tmats[nt]
+        Fl = [sp.assemble_load(C, sp.project_f(t, w.random_modes(sd), 0)).T for sd in w.rhs_seeds("batch", 8, pidx)]
+        F = torch.from_numpy(np.ascontiguousarray(np.stack(Fl))).to("cuda:0")
+        Fd.append(F)
+        Ud.append(torch.empty_like(F))
+        probs.append(stfd.Problem(sp, A, M, precision=precision, rtol=RTOL, max_refine=30))
+        dofs += sp.Mx * nt * 8
+        if pidx % 12 == 11:
+            print(f"# {precision}: {pidx + 1}/96 problems set up ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+                  flush=True)
+    setup_s = time.perf_counter() - t0
+    batch = stfd.Batch(probs)
+    for _ in range(warmup):
+        batch.factor()
+        batch.solve(Fd, Ud)
+    torch.cuda.synchronize()
+    for p in probs:
+        p.profile(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        batch.factor()
+        rc, reps = batch.solve(Fd, Ud)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    prof = {}
+    work = {}
+    for p, F in zip(probs, Fd):
+        pr = p.profile_read()
+        nsys = p.setup_report["n_sys"]
+        for k, (ms, n) in pr.items():
+            tot = prof.setdefault(k, [0.0, 0])
+            tot[0] += ms
+            tot[1] += n
+            kind, units = stage_work(k, p.Mx, p.Nt, p.setup_report["half_band"], nsys, F.shape[0], 4)
+            if kind:
+                work[k] = work.get(k, 0.0) + (units or 0.0) * n
+        p.profile(False)
+    iters = max(r["iterations"] for r in reps)
+    res = max(r["rel_residual"][r["iterations"] - 1] for r in reps)
+    out = {"sec": sec, "setup_s": setup_s, "dofs": dofs, "prof": prof, "work": work, "iterations": iters,
+           "rel_residual": res, "converged": all(r["converged"] for r in reps), "kappa2": max(
+               p.setup_report["kappa2"] for p in probs)}
+    del batch, probs, Fd, Ud
+    return out
+
+
+def main_batch(args):
+    res = {}
+    for prec in ("fp32", "fp64"):
+        res[prec] = run_batch(args.steps, args.warmup, prec)
+        r = res[prec]
+        print(f"# {prec}: {r['sec'] * 1e3:.1f} ms/step, max iterations {r['iterations']}, max residual "
+              f"{r['rel_residual']:.2e}, all converged {r['converged']}", file=sys.stderr, flush=True)
+    m = res["fp32"]
+    prof = m["prof"]
+    dom = max(prof, key=lambda k: prof[k][0])
+    ms_tot, launches = prof[dom]
+    kind = stage_work(dom, 1, 1, 1, 1, 1, 4)[0]
+    achieved = m["work"].get(dom, 0.0) / (ms_tot * 1e-3)
+    if kind == "hbm":
+        roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
+    else:
+        peak = PEAK["fp64_mfma"] if dom in FP64_STAGES_IN_FP32_FORM else PEAK["fp32_mfma"]
+        roof = {"bound": "mfma", "achieved": achieved / 1e12, "peak": peak, "unit": "TFLOP/s"}
+    roof.update({"frac": roof["achieved"] / roof["peak"], "traffic": None, "kernel": dom,
+                 "avg_launch_ms": ms_tot / max(launches, 1), "work_per_launch": m["work"].get(dom, 0.0) / max(launches, 1)})
+    out = {
+        "metric": METRIC, "value": m["dofs"] / m["sec"], "unit": "DOF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": m["sec"] * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 complex (factor, sweeps, second forward GEMM) + f64 (first forward GEMM, back transform, "
+                 "residual, update)",
+        "data": "synthetic",
+        "config": {"workload": "batch96", "description": WORKLOADS["batch96"]["desc"], "problems": 96,
+                   "nrhs_per_problem": 8, "dof_rhs_total": m["dofs"], "rtol": RTOL},
+        "roofline": roof, "cpu_baseline": None,
+        "fp64_fd": {"value": res["fp64"]["dofs"] / res["fp64"]["sec"], "ms_per_step": res["fp64"]["sec"] * 1e3,
+                    "iterations": res["fp64"]["iterations"], "rel_residual": res["fp64"]["rel_residual"]},
+        "speedup_fp32_vs_fp64": res["fp64"]["sec"] / m["sec"],
+        "iterations": m["iterations"], "rel_residual": m["rel_residual"], "kappa2_X": m["kappa2"],
+        "setup_ms": m["setup_s"] * 1e3,
+        "stages_ms_per_step": {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
+                               for k, v in prof.items()},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +392,10 @@ def main():
               "(see DESIGN.md), not an implementation.  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     spec = WORKLOADS[args.workload]
+    if args.workload == "batch96":
+        print(f"# workload batch96: {spec['desc']}", file=sys.stderr, flush=True)
+        main_batch(args)
+        return
     mesh, t, modes = build_inputs(spec)
     print(f"# workload {args.workload}: {spec['desc']}", file=sys.stderr, flush=True)
 

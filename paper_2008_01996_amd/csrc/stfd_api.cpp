@@ -7,6 +7,7 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -292,11 +293,37 @@ int ensure_work(stfd_problem* p, int nrhs) {
 
 }  // namespace
 
+// The decomposition depends only on the time pencil: problems that share
+// A_t and M_t (the same time mesh) reuse it.  Keyed by the exact bytes of
+// both matrices; a few entries are kept for the life of the process.
+static std::mutex g_decomp_mutex;
+static std::vector<std::pair<std::vector<double>, Decomp>> g_decomp_cache;
+
+static int decompose_cached(int n, const double* At, const double* Mt, Decomp& D) {
+    std::vector<double> key((size_t)2 * n * n);
+    std::memcpy(key.data(), At, (size_t)n * n * sizeof(double));
+    std::memcpy(key.data() + (size_t)n * n, Mt, (size_t)n * n * sizeof(double));
+    {
+        std::lock_guard<std::mutex> lock(g_decomp_mutex);
+        for (const auto& e : g_decomp_cache)
+            if (e.first.size() == key.size() && std::memcmp(e.first.data(), key.data(), key.size() * sizeof(double)) == 0) {
+                D = e.second;
+                return STFD_OK;
+            }
+    }
+    const int rc = decompose(n, At, Mt, D);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_decomp_mutex);
+    if (g_decomp_cache.size() >= 8) g_decomp_cache.erase(g_decomp_cache.begin());
+    g_decomp_cache.emplace_back(std::move(key), D);
+    return STFD_OK;
+}
+
 extern "C" int stfd_time_decompose(int Nt, const double* At, const double* Mt, double* lam_re, double* lam_im,
                                    double* X_re, double* X_im, double* sigma, stfd_setup_report* rep) {
     if (Nt < 1 || !At || !Mt) return fail(STFD_EINVAL, "time_decompose: bad arguments");
     Decomp D;
-    int rc = decompose(Nt, At, Mt, D);
+    int rc = decompose_cached(Nt, At, Mt, D);
     if (rc) return rc;
     for (int k = 0; k < Nt; ++k) {
         if (lam_re) lam_re[k] = D.lam[k].real();
@@ -327,7 +354,7 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
         return fail(STFD_EINVAL, "fd_setup: bad options");
     const auto t0 = std::chrono::steady_clock::now();
     Decomp D;
-    int rc = decompose(Nt, At, Mt, D);
+    int rc = decompose_cached(Nt, At, Mt, D);
     if (rc) return rc;
 
     auto* p = new (std::nothrow) stfd_problem();
