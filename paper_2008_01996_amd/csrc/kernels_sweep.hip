@@ -28,6 +28,8 @@
 // column k, imaginary parts in column n_sys + k.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -619,14 +621,21 @@ static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs,
     return hipGetLastError();
 }
 
-// Block sizes keep a block near 4100 complex entries (32-64 KB) in every
-// configuration: FP32 32 columns (bp <= 128) or 16 (bp <= 256), FP64 16 or 8.
+// Block sizes: a block holds near 4100 complex entries (FP32 32 columns for
+// bp <= 128, 16 for bp <= 256; FP64 16 or 8).  With three or more right-hand
+// sides the backward sweep's diagonal chain (work per column proportional to
+// nrhs * CB) bounds it, and its blocks halve for bp <= 128; the forward
+// sweep is then bound by its far update, which smaller blocks make longer.
+constexpr int MULTI_RHS = 3;
+
 template <typename T>
 size_t sweep_smem(int bp) {
     if constexpr (sizeof(T) == 4)
-        return bp <= 128 ? smem_elems<T, 32, 128>(bp) * 4 : smem_elems<T, 16, 256>(bp) * 4;
+        return bp <= 128 ? std::max(smem_elems<T, 32, 128>(bp), smem_elems<T, 16, 128>(bp)) * 4
+                         : smem_elems<T, 16, 256>(bp) * 4;
     else
-        return bp <= 128 ? smem_elems<T, 16, 128>(bp) * 8 : smem_elems<T, 8, 256>(bp) * 8;
+        return bp <= 128 ? std::max(smem_elems<T, 16, 128>(bp), smem_elems<T, 8, 128>(bp)) * 8
+                         : smem_elems<T, 8, 256>(bp) * 8;
 }
 
 template <typename T>
@@ -646,9 +655,11 @@ template <typename T>
 hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
+        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128) return launch_bwd<T, 32, 128>(LB, Mx, bp, nsys, nrhs, W, st);
         return launch_bwd<T, 16, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     } else {
+        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd<T, 8, 128>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128) return launch_bwd<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
         return launch_bwd<T, 8, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     }
