@@ -160,6 +160,53 @@ __device__ __forceinline__ void forward_far_update(const cplx<T>* L, const T* YR
     }
 }
 
+// The same for several right-hand sides at once: each L entry is read once
+// and applied to all NRS of them (right-hand sides past nr see zero y).
+template <typename T, int CB, int PW>
+__device__ __forceinline__ void forward_far_update_multi(const cplx<T>* L, const T* YR, const T* YI, T* QR, T* QI,
+                                                         int c0, int nb, int Mx, int bp, int ls, int nr, int cs,
+                                                         int ring, int zero, int li) {
+    constexpr int KP = CB / PW;
+    constexpr int IPP = NL / PW;
+    const int part = PW == 1 ? 0 : (li & 63) >> 5;
+    const int slot_item = PW == 1 ? li : (li >> 6) * 32 + (li & 31);
+    const int nrow = bp - CB;
+    for (int m0 = 0; m0 < nrow; m0 += IPP) {
+        const int m = m0 + slot_item;
+        const int rr = CB + m;
+        const bool row_ok = m < nrow && c0 + CB + rr < Mx;
+        const int kmin = CB + rr - bp;
+        T ar[NRS], ai[NRS];
+#pragma unroll
+        for (int t = 0; t < NRS; ++t) ar[t] = ai[t] = T(0);
+#pragma unroll 4
+        for (int kk = 0; kk < KP; ++kk) {
+            const int k = part * KP + kk;
+            const int e = row_ok && k < nb && k >= kmin ? k * ls + CB + rr - k : zero;
+            const cplx<T> l = L[e];
+#pragma unroll
+            for (int t = 0; t < NRS; ++t) cmac(ar[t], ai[t], l.re, l.im, YR[k * NRS + t], YI[k * NRS + t]);
+        }
+        if constexpr (PW == 2) {
+#pragma unroll
+            for (int t = 0; t < NRS; ++t) {
+                ar[t] += __shfl_xor(ar[t], 32, 64);
+                ai[t] += __shfl_xor(ai[t], 32, 64);
+            }
+        }
+        if (row_ok && part == 0) {
+            int s = cs + rr;
+            s = s >= ring ? s - ring : s;
+#pragma unroll
+            for (int t = 0; t < NRS; ++t)
+                if (t < nr) {
+                    QR[s * NRS + t] -= ar[t];
+                    QI[s * NRS + t] -= ai[t];
+                }
+        }
+    }
+}
+
 // Backward, off the critical path (waves 1-3): for the full block at c0 and
 // every column k, partial sums over rows r = c0 + 2 CB + m (m < bp - CB) of
 // L[r, c0 + k] z[r][t].  Lane li takes column k = li % CB and the RPC rows of
@@ -191,6 +238,44 @@ __device__ __forceinline__ void backward_far_sums(const cplx<T>* L, const T* ZR,
             SR[(w * CB + k) * NRS + t] = ar;
             SI[(w * CB + k) * NRS + t] = ai;
         }
+    }
+}
+
+// The same for several right-hand sides at once (each L entry read once;
+// finished z of right-hand sides past nr are zero).
+template <typename T, int CB, int RPC>
+__device__ __forceinline__ void backward_far_sums_multi(const cplx<T>* L, const T* ZR, const T* ZI, T* SR, T* SI,
+                                                        int c0, int Mx, int bp, int ls, int nr, int cs, int ring,
+                                                        int zero, int li) {
+    const int k = li % CB, ch = li / CB, w = li >> 6;
+    const int nrow = bp - CB;
+    T ar[NRS], ai[NRS];
+#pragma unroll
+    for (int t = 0; t < NRS; ++t) ar[t] = ai[t] = T(0);
+#pragma unroll 4
+    for (int i = 0; i < RPC; ++i) {
+        const int m = ch * RPC + i;
+        const int d = 2 * CB + m - k;
+        const bool on = m < nrow && d <= bp && c0 + 2 * CB + m < Mx;
+        const cplx<T> l = L[on ? k * ls + d : zero];
+        int sl = cs + CB + min(m, max(nrow - 1, 0));
+        sl = sl >= ring ? sl - ring : sl;
+#pragma unroll
+        for (int t = 0; t < NRS; ++t) cmac(ar[t], ai[t], l.re, l.im, ZR[sl * NRS + t], ZI[sl * NRS + t]);
+    }
+#pragma unroll
+    for (int t = 0; t < NRS; ++t)
+        for (int off = CB; off < 64; off <<= 1) {
+            ar[t] += __shfl_xor(ar[t], off, 64);
+            ai[t] += __shfl_xor(ai[t], off, 64);
+        }
+    if ((li & 63) < CB) {
+#pragma unroll
+        for (int t = 0; t < NRS; ++t)
+            if (t < nr) {
+                SR[(w * CB + k) * NRS + t] = ar[t];
+                SI[(w * CB + k) * NRS + t] = ai[t];
+            }
     }
 }
 
@@ -243,7 +328,7 @@ __device__ __forceinline__ void chain2(T& vr, T& vi, T& ar, T& ai, const cplx<T>
 }  // namespace
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int BPC>
+template <typename T, int CB, int BPC, bool MULTI>
 __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp, int nsys,
                                                            int nrhs, const T* __restrict__ G, T* __restrict__ W) {
     using C = Cfg<T, CB, BPC>;
@@ -289,6 +374,10 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         PR[q] = 0;
         PI[q] = 0;
     }
+    for (int q = tid; q < 2 * CB * NRS; q += NT) {     // right-hand sides past nr stay zero
+        YR[q] = 0;
+        YI[q] = 0;
+    }
 
     for (int q = tid; q < NSLOT; q += NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
 
@@ -325,12 +414,21 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                     const int yo = (i & 1) * CB * NRS;
                     const cplx<T>* L = reinterpret_cast<const cplx<T>*>(LR);
                     const int nbi = min(CB, Mx - i * CB);
-                    if ((bp - CB) * nr * 2 <= NL)
+                    const bool pw2 = (bp - CB) * 2 <= NL;
+                    if constexpr (MULTI) {
+                        if (pw2)
+                            forward_far_update_multi<T, CB, 2>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls,
+                                                               nr, cs, ring, C::ZERO, li);
+                        else
+                            forward_far_update_multi<T, CB, 1>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls,
+                                                               nr, cs, ring, C::ZERO, li);
+                    } else if (pw2) {
                         forward_far_update<T, CB, 2>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls, nr, cs,
                                                      ring, C::ZERO, li);
-                    else
+                    } else {
                         forward_far_update<T, CB, 1>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls, nr, cs,
                                                      ring, C::ZERO, li);
+                    }
                 }
                 __syncthreads();
                 cs = wrap(cs + CB);
@@ -421,7 +519,7 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int BPC>
+template <typename T, int CB, int BPC, bool MULTI>
 __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp,
                                                             int nsys, int nrhs, T* __restrict__ W) {
     using C = Cfg<T, CB, BPC>;
@@ -502,8 +600,12 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                     const T* LR = slots + ((s + 1) % NSLOT) * C::SLOT;
                     const int so = ((s + 1) & 1) * 3 * CB * NRS;
                     constexpr int RPC = (BPC - CB + NL / CB - 1) / (NL / CB);
-                    backward_far_sums<T, CB, RPC>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so, SI + so,
-                                                  a * CB, Mx, bp, ls, nr, cs, ring, C::ZERO, li);
+                    if constexpr (MULTI)
+                        backward_far_sums_multi<T, CB, RPC>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so,
+                                                            SI + so, a * CB, Mx, bp, ls, nr, cs, ring, C::ZERO, li);
+                    else
+                        backward_far_sums<T, CB, RPC>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so, SI + so,
+                                                      a * CB, Mx, bp, ls, nr, cs, ring, C::ZERO, li);
                 }
                 __syncthreads();
                 cs = cs >= CB ? cs - CB : cs - CB + ring;
@@ -595,28 +697,28 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int BPC>
+template <typename T, int CB, int BPC, bool MULTI>
 static hipError_t launch_fwd(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
                              hipStream_t st) {
     const size_t smem = smem_elems<T, CB, BPC>(bp) * sizeof(T);
-    hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, BPC>,
+    hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, BPC, MULTI>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
-    hipLaunchKernelGGL((sweep_forward_kernel<T, CB, BPC>), grid, dim3(NT), smem, st,
+    hipLaunchKernelGGL((sweep_forward_kernel<T, CB, BPC, MULTI>), grid, dim3(NT), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<const T*>(G),
                        static_cast<T*>(W));
     return hipGetLastError();
 }
 
-template <typename T, int CB, int BPC>
+template <typename T, int CB, int BPC, bool MULTI>
 static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
     const size_t smem = smem_elems<T, CB, BPC>(bp) * sizeof(T);
-    hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, BPC>,
+    hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, BPC, MULTI>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
-    hipLaunchKernelGGL((sweep_backward_kernel<T, CB, BPC>), grid, dim3(NT), smem, st,
+    hipLaunchKernelGGL((sweep_backward_kernel<T, CB, BPC, MULTI>), grid, dim3(NT), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W));
     return hipGetLastError();
 }
@@ -627,6 +729,11 @@ static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs,
 // nrhs * CB) bounds it, and its blocks halve for bp <= 128; the forward
 // sweep is then bound by its far update, which smaller blocks make longer.
 constexpr int MULTI_RHS = 3;
+// From these right-hand-side counts on, the far-band work reads each L entry
+// once for all right-hand sides of a workgroup (kernels built apart, so the
+// one-right-hand-side code keeps its own schedule).
+constexpr int FWD_MULTI_MIN = 5;
+constexpr int BWD_MULTI_MIN = 6;
 
 template <typename T>
 size_t sweep_smem(int bp) {
@@ -638,16 +745,29 @@ size_t sweep_smem(int bp) {
                          : smem_elems<T, 8, 256>(bp) * 8;
 }
 
+template <typename T, int CB, int BPC>
+static hipError_t launch_fwd_any(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
+                                 hipStream_t st) {
+    return nrhs >= FWD_MULTI_MIN ? launch_fwd<T, CB, BPC, true>(LB, Mx, bp, nsys, nrhs, G, W, st)
+                                 : launch_fwd<T, CB, BPC, false>(LB, Mx, bp, nsys, nrhs, G, W, st);
+}
+
+template <typename T, int CB, int BPC>
+static hipError_t launch_bwd_any(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
+    return nrhs >= BWD_MULTI_MIN ? launch_bwd<T, CB, BPC, true>(LB, Mx, bp, nsys, nrhs, W, st)
+                                 : launch_bwd<T, CB, BPC, false>(LB, Mx, bp, nsys, nrhs, W, st);
+}
+
 template <typename T>
 hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
                                hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
-        if (bp <= 128) return launch_fwd<T, 32, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        return launch_fwd<T, 16, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        if (bp <= 128) return launch_fwd_any<T, 32, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        return launch_fwd_any<T, 16, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
     } else {
-        if (bp <= 128) return launch_fwd<T, 16, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        return launch_fwd<T, 8, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        if (bp <= 128) return launch_fwd_any<T, 16, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        return launch_fwd_any<T, 8, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
     }
 }
 
@@ -655,13 +775,13 @@ template <typename T>
 hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
-        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128) return launch_bwd<T, 32, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        return launch_bwd<T, 16, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_any<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128) return launch_bwd_any<T, 32, 128>(LB, Mx, bp, nsys, nrhs, W, st);
+        return launch_bwd_any<T, 16, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     } else {
-        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd<T, 8, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128) return launch_bwd<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        return launch_bwd<T, 8, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_any<T, 8, 128>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128) return launch_bwd_any<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
+        return launch_bwd_any<T, 8, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     }
 }
 

@@ -119,6 +119,88 @@ def test_wide_bands(precision, ncx, ncy, nrhs):
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 
+# Right-hand-side counts that take every sweep variant (one; five and six,
+# where the far-band work switches to reading L once for all right-hand
+# sides; eight, a full group; nine, a full group and a group of one) on
+# meshes of padded half-bandwidth 16, 128 and 256.
+SWEEP_CASES = [(9, 9, 1), (9, 9, 6), (120, 3, 5), (120, 3, 9), (250, 3, 8)]
+SWEEP_IDS = ["sq9_rhs1", "sq9_rhs6", "band120_rhs5", "band120_rhs9", "band250_rhs8"]
+UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ncx,ncy,nrhs", SWEEP_CASES, ids=SWEEP_IDS)
+def test_spatial_step_matches_oracle_solves(precision, ncx, ncy, nrhs):
+    """Step 3 alone (band LDL^T and both sweeps) against the oracle's sparse
+    complex solves of (M_x + lambda_k A_x) z = g, per system and right-hand
+    side.  The systems' eigenvalues must match the oracle's; the oracle solves
+    with its own.  Bound: banded LU without pivoting has backward error of
+    order (b + 1) u |L||U| (Higham, Thm. 9.3), and for these complex
+    symmetric systems with positive definite real and imaginary parts |L||U|
+    stays of the size of |S|, so the relative forward error is within
+    4 (b + 1) u kappa_2(S_k)."""
+    mesh = w.rect_mesh(ncx, ncy)
+    t = w.graded_times(7)                       # odd N_t: three pairs and one real eigenvalue
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, _ = sm.assemble(mesh)
+    dec = so.decompose(At, Mt)
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision=precision)
+    prob.factor()
+    lam = prob.system_lambdas()
+    n, m = len(lam), Mx.shape[0]
+    assert prob.setup_report["n_real"] == 1
+    rng = np.random.default_rng(8000 + nrhs)
+    G = rng.standard_normal((nrhs, 2 * n, m))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Gd = torch.from_numpy(G).to("cuda:0", dt)
+    Z = torch.empty_like(Gd)
+    prob.spatial_solve(Gd, Z)
+    torch.cuda.synchronize()
+    Z = Z.double().cpu().numpy()
+    b = prob.setup_report["half_band"]
+    u = UNIT_ROUNDOFF[precision]
+    for k in range(n):
+        j = int(np.argmin(np.abs(dec.lam - lam[k])))
+        assert abs(dec.lam[j] - lam[k]) <= 1e-10 * abs(dec.lam[j])
+        S = (Mx + dec.lam[j] * Ax).toarray()
+        tol = 4 * (b + 1) * u * np.linalg.cond(S)
+        for q in range(nrhs):
+            g = G[q, k] + 1j * G[q, n + k]
+            zo = so._spatial_solve((Mx, Ax, dec.lam[j], g))
+            z = Z[q, k] + 1j * Z[q, n + k]
+            err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+            assert err <= tol, (k, q, err, tol)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ncx,ncy,nrhs", SWEEP_CASES, ids=SWEEP_IDS)
+def test_single_application_matches_oracle_fd(precision, ncx, ncy, nrhs):
+    """One application of Algorithm FD, no refinement (the refinement would
+    hide a wrong step: it only needs a contraction), against the oracle's
+    Algorithm FD.  Each side's error is within N_t u kappa_2(X_t) (transform
+    products of length N_t, amplified by the eigenvector matrix's condition
+    number), u the unit roundoff of the stages in the working precision, so
+    the two agree within twice that."""
+    mesh = w.rect_mesh(ncx, ncy)
+    t = w.uniform_times(12)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[7000 + r for r in range(nrhs)])
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision=precision)
+    prob.factor()
+    X = _to_dev(Fs)
+    U = torch.empty_like(X)
+    prob.apply(X, U)
+    torch.cuda.synchronize()
+    Us = [u.T.copy() for u in U.cpu().numpy()]
+    dec = so.decompose(At, Mt)
+    tol = 2 * (len(t) - 1) * UNIT_ROUNDOFF[precision] * np.linalg.cond(dec.X)
+    worst = 0.0
+    for Fq, Uq in zip(Fs, Us):
+        Uo = so.fd(At, Mt, Mx, Ax, Fq, dec)
+        worst = max(worst, np.linalg.norm(Uq - Uo) / np.linalg.norm(Uo))
+    print(f"  one application: worst rel diff vs oracle FD {worst:.2e} (bound {tol:.2e})")
+    assert worst <= tol
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_lshape_variable_rows(precision):
     """L-shape (rows of 7 and 15 interior nodes), paper time mesh level 2."""
