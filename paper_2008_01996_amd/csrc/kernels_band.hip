@@ -237,7 +237,10 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 
     // window columns [0, ring)
     const int wcols = min(ring, Mx);
-    for (int e = tid; e < ring * bp1; e += 256) Wn[e] = e < wcols * bp1 ? base[e] : zero;
+    for (int e = tid; e < ring * bp1; e += 256) {       // values, not a choice of lvalues (that would
+        const bool in = e < wcols * bp1;                 // put the operands in scratch memory)
+        Wn[e] = in ? cplx<T>{base[e].re, base[e].im} : cplx<T>{0, 0};
+    }
     if (tid == 0) Wn[ZE] = zero;
     // columns of entry tid + 256 j of a 16-column block (fixed for the whole run)
     int ecol[EP];
@@ -248,7 +251,11 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
     auto prefetch = [&](int c0) {
         const size_t b0 = (size_t)c0 * bp1;
 #pragma unroll
-        for (int j = 0; j < EP; ++j) pf[j] = base[min(b0 + tid + 256 * j, total - 1)];
+        for (int j = 0; j < EP; ++j) {          // field by field: keeps pf in registers for complex double
+            const cplx<T>* e = base + min(b0 + tid + 256 * j, total - 1);
+            pf[j].re = e->re;
+            pf[j].im = e->im;
+        }
     };
     prefetch(ring);
     __syncthreads();
@@ -367,7 +374,9 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
                 const int e = tid + 256 * j;
                 if (e < 16 * bp1) {
                     if (ecol[j] < nb) dst[e] = P[e];
-                    P[e] = ecol[j] < ncol_in ? pf[j] : zero;
+                    const bool in = ecol[j] < ncol_in;
+                    P[e].re = in ? pf[j].re : T(0);
+                    P[e].im = in ? pf[j].im : T(0);
                 }
             }
         }

@@ -76,8 +76,14 @@ __device__ __forceinline__ void fetch(cplx<T> (&l)[EL], cplx<T> (&r)[ER], const 
     const int c0 = b * CB;
     const int last = min(CB, Mx - c0) * bp1 - 1;
     const cplx<T>* src = base + (size_t)c0 * bp1;
+    // field by field: a whole-struct copy of a 16-byte complex double stays a
+    // memory copy that keeps l in scratch memory instead of registers
 #pragma unroll
-    for (int j = 0; j < EL; ++j) l[j] = src[min(li + NL * j, last)];
+    for (int j = 0; j < EL; ++j) {
+        const cplx<T>* e = src + min(li + NL * j, last);
+        l[j].re = e->re;
+        l[j].im = e->im;
+    }
     // right-hand-side values of rows blk*CB + rowoff + q / NRS, q in [0, CB * NRS)
 #pragma unroll
     for (int j = 0; j < ER; ++j) {
@@ -111,7 +117,10 @@ __device__ __forceinline__ void deposit(const cplx<T> (&l)[EL], const cplx<T> (&
     T* GR = slot + 2 * EPB;
     T* GI = GR + ERB;
 #pragma unroll
-    for (int j = 0; j < EL; ++j) L[off[j]] = l[j];
+    for (int j = 0; j < EL; ++j) {
+        L[off[j]].re = l[j].re;
+        L[off[j]].im = l[j].im;
+    }
 #pragma unroll
     for (int j = 0; j < ER; ++j) {
         GR[li + NL * j] = r[j].re;
@@ -395,18 +404,14 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         fetch<T, CB, C::EL, C::ER>(la, ra, base, 2, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
         __syncthreads();
         int cs = 0;                               // c0 of the current step, mod ring
-        for (int s0 = 0; s0 < nbar; s0 += 2) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int s = s0 + h;
-                T* dst = slots + ((s + 1) % NSLOT) * C::SLOT;
-                if (h == 0) {
-                    deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lb, rb, off, dst, li);
-                    fetch<T, CB, C::EL, C::ER>(lb, rb, base, s + 3, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
-                } else {
-                    deposit<T, C::EPB, C::ERB, C::EL, C::ER>(la, ra, off, dst, li);
-                    fetch<T, CB, C::EL, C::ER>(la, ra, base, s + 3, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
-                }
+        // One step on register set (lx, rx).  The two sets are passed in
+        // straight-line calls, never chosen by a branch, so that both stay in
+        // registers (a choice between them would put them in scratch memory).
+        auto step = [&](int s, cplx<T>(&lx)[C::EL], cplx<T>(&rx)[C::ER]) {
+            T* dst = slots + ((s + 1) % NSLOT) * C::SLOT;
+            deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lx, rx, off, dst, li);
+            fetch<T, CB, C::EL, C::ER>(lx, rx, base, s + 3, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
+            {
                 // rows two or more blocks below block s - 1
                 const int i = s - 1;
                 if (i >= 0 && i < nblk) {
@@ -430,9 +435,13 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                                                      ring, C::ZERO, li);
                     }
                 }
-                __syncthreads();
-                cs = wrap(cs + CB);
             }
+            __syncthreads();
+            cs = wrap(cs + CB);
+        };
+        for (int s0 = 0; s0 < nbar; s0 += 2) {
+            step(s0, lb, rb);
+            step(s0 + 1, la, ra);
         }
         return;
     }
@@ -580,20 +589,13 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
         fetch<T, CB, C::EL, C::ER>(lb, rb, base, nblk - 4, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
         __syncthreads();
         int cs = cs0;
-        for (int s0 = 0; s0 < nbar; s0 += 2) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int s = s0 + h;
-                T* dst = slots + ((s + 2) % NSLOT) * C::SLOT;
-                if (h == 0) {
-                    deposit<T, C::EPB, C::ERB, C::EL, C::ER>(la, ra, off, dst, li);
-                    fetch<T, CB, C::EL, C::ER>(la, ra, base, nblk - 1 - (s + 4), nblk, Mx, bp1, wre, wim, rstride,
-                                               nr, 0, li);
-                } else {
-                    deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lb, rb, off, dst, li);
-                    fetch<T, CB, C::EL, C::ER>(lb, rb, base, nblk - 1 - (s + 4), nblk, Mx, bp1, wre, wim, rstride,
-                                               nr, 0, li);
-                }
+        // one step on register set (lx, rx), straight-line calls as in the forward sweep
+        auto step = [&](int s, cplx<T>(&lx)[C::EL], cplx<T>(&rx)[C::ER]) {
+            T* dst = slots + ((s + 2) % NSLOT) * C::SLOT;
+            deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lx, rx, off, dst, li);
+            fetch<T, CB, C::EL, C::ER>(lx, rx, base, nblk - 1 - (s + 4), nblk, Mx, bp1, wre, wim, rstride, nr, 0,
+                                       li);
+            {
                 // sums over rows two or more blocks below the block of step s + 1
                 const int a = nblk - 2 - s;
                 if (a >= 0) {
@@ -607,9 +609,13 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                         backward_far_sums<T, CB, RPC>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so, SI + so,
                                                       a * CB, Mx, bp, ls, nr, cs, ring, C::ZERO, li);
                 }
-                __syncthreads();
-                cs = cs >= CB ? cs - CB : cs - CB + ring;
             }
+            __syncthreads();
+            cs = cs >= CB ? cs - CB : cs - CB + ring;
+        };
+        for (int s0 = 0; s0 < nbar; s0 += 2) {
+            step(s0, la, ra);
+            step(s0 + 1, lb, rb);
         }
         return;
     }
