@@ -390,18 +390,26 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 // ---------------------------------------------------------------------------
 // FP32 with padded half-bandwidth 128: the trailing window in registers.
 // Column block B (columns 16B .. 16B + 15) lies in the trailing window of
-// panels q with q < B <= q + 8; there it sits at position m = B - q - 1 and is
-// owned by wave B mod 4.  Its band rows 16B .. 16B + 127 (row blocks B ..
-// B + 7) are kept as eight 16x16 MFMA accumulator tiles, positions 0-3 in
-// slot 0 and 4-7 in slot 1, and every trailing update accumulates into them
-// directly.  Row block B + 8 of the block is only touched by the block's own
-// panel.  When block q becomes the panel its owner writes its tiles to the
-// LDS panel buffer, moves the block at position 4 down to slot 0 and takes
-// the block entering at position 7 (prefetched into registers a panel ahead)
-// into slot 1.  The panel is factored in registers as in the window kernel,
-// written to HBM once, and its rows give the tile operands.
+// panels q with q < B <= q + 8; there it sits at position m = B - q - 1.  Its
+// band rows 16B .. 16B + 127 (row blocks B .. B + 7) are eight 16x16 MFMA
+// accumulator tiles; tile ra (row block B + ra) is owned by wave
+// (B + own_shift(ra)) mod 4, in that wave's slot 0 at positions 0-3 and slot
+// 1 at positions 4-7, and every trailing update accumulates into it directly.
+// The shifts give every wave 9 of the 36 tiles a panel updates (owning whole
+// blocks would give 12, 10, 8 and 6) and spread a block's hand-over over the
+// waves.  Row block B + 8 of the block is only touched by the block's own
+// panel.  When block q becomes the panel the owners of its tiles write them
+// to the LDS panel buffer, move their tile of the block at position 4 down
+// to slot 0 and take the block entering at position 7 (prefetched into
+// registers a panel ahead) into slot 1.  The panel is factored in registers
+// as in the window kernel, written to HBM once, and its rows give the tile
+// operands.
 // ---------------------------------------------------------------------------
 constexpr int RPS = 17;                                   // panel buffer row stride (complex)
+
+__device__ __forceinline__ constexpr int own_shift(int ra) {
+    return ra == 2 || ra == 3 ? 1 : ra == 5 ? 2 : ra >= 6 ? 3 : 0;
+}
 
 __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restrict__ LB, int Mx,
                                                            int* __restrict__ flag) {
@@ -424,16 +432,18 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
     auto tile_ok = [&](int B, int ra, int j) {
         return B < nblk && 16 * B + 4 * lk + j < Mx && 16 * ra + li - 4 * lk - j >= 0;
     };
-    auto tile_load = [&](int B, cplx<T> (&v)[8][4]) {
+    auto tile_load = [&](int B, int ra, cplx<T> (&v)[4]) {
 #pragma unroll
-        for (int ra = 0; ra < 8; ++ra)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int c = 16 * B + 4 * lk + j;
-                const int d = 16 * ra + li - 4 * lk - j;
-                v[ra][j] = base[tile_ok(B, ra, j) ? (size_t)c * bp1 + d : 0];
-            }
+        for (int j = 0; j < 4; ++j) {
+            const int c = 16 * B + 4 * lk + j;
+            const int d = 16 * ra + li - 4 * lk - j;
+            const cplx<T>* e = base + (tile_ok(B, ra, j) ? (size_t)c * bp1 + d : 0);
+            v[j].re = e->re;
+            v[j].im = e->im;
+        }
     };
+    // does this wave own tile ra of column block B
+    auto owns = [&](int B, int ra) { return ((B + own_shift(ra)) & 3) == wave; };
     // row block 8 of column block B: entry (row 128 + tid / 16, column tid % 16)
     const int r8r = 128 + (tid >> 4), r8c = tid & 15;
     auto row8_ok = [&](int B) { return B < nblk && 16 * B + r8c < Mx && r8r - r8c <= bp; };
@@ -451,21 +461,25 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
             const cplx<T> x = base[ok ? (size_t)c * bp1 + d : 0];
             P[r * RPS + c] = ok ? x : zero;
         }
-        const int b0 = wave == 0 ? 4 : wave;
 #pragma unroll
-        for (int sl = 0; sl < 2; ++sl) {
-            tile_load(b0 + 4 * sl, pf);
+        for (int ra = 0; ra < 8; ++ra) {
+            int b0 = (wave - own_shift(ra)) & 3;         // this wave's blocks of tile ra: b0, b0 + 4
+            b0 = b0 == 0 ? 4 : b0;
 #pragma unroll
-            for (int ra = 0; ra < 8; ++ra)
+            for (int sl = 0; sl < 2; ++sl) {
+                tile_load(b0 + 4 * sl, ra, pf[ra]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const bool ok = tile_ok(b0 + 4 * sl, ra, j);
                     accR[sl][ra][j] = ok ? pf[ra][j].re : T(0);
                     accI[sl][ra][j] = ok ? pf[ra][j].im : T(0);
                 }
+            }
         }
     }
-    if (wave == 1) tile_load(9, pf);
+#pragma unroll
+    for (int ra = 0; ra < 8; ++ra)
+        if (owns(9, ra)) tile_load(9, ra, pf[ra]);
     cplx<T> r8 = row8_load(1);
     int ecol[EP], erow[EP];
 #pragma unroll
@@ -480,16 +494,15 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
         const int p0 = 16 * q;
         const int nb = min(16, Mx - p0);
         if (q > 0) {
-            // ---- hand over: block q from its owner's slot 0 into P; the block
-            // at position 4 moves to slot 0, block q + 8 enters slot 1
-            if (wave == (q & 3)) {
+            // ---- hand over: the tiles of block q from their owners' slot 0
+            // into P; the block at position 4 moves to slot 0, block q + 8
+            // enters slot 1
 #pragma unroll
-                for (int ra = 0; ra < 8; ++ra)
+            for (int ra = 0; ra < 8; ++ra) {
+                if (owns(q, ra)) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         P[(16 * ra + li) * RPS + 4 * lk + j] = cplx<T>{accR[0][ra][j], accI[0][ra][j]};
-#pragma unroll
-                for (int ra = 0; ra < 8; ++ra) {
                     accR[0][ra] = accR[1][ra];
                     accI[0][ra] = accI[1][ra];
 #pragma unroll
@@ -502,7 +515,9 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
             }
             P[r8r * RPS + r8c] = row8_ok(q) ? r8 : zero;
             // prefetch for panel q + 1
-            if (wave == ((q + 1) & 3)) tile_load(q + 9, pf);
+#pragma unroll
+            for (int ra = 0; ra < 8; ++ra)
+                if (owns(q + 9, ra)) tile_load(q + 9, ra, pf[ra]);
             r8 = row8_load(q + 1);
         }
         __syncthreads();
@@ -569,9 +584,10 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
             }
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
-                if (((q + 1 + m) & 3) == wave && q + 1 + m < nblk) {
+                if (q + 1 + m < nblk) {
 #pragma unroll
                     for (int ra = 0; ra < 8 - m; ++ra) {
+                        if (!owns(q + 1 + m, ra)) continue;
                         V4 cr = accR[m >= 4][ra], ci = accI[m >= 4][ra];
 #pragma unroll
                         for (int kk = 0; kk < 4; ++kk) {
