@@ -37,14 +37,20 @@ namespace stfd {
 
 namespace {
 
-constexpr int NT = 256;      // threads per workgroup
-constexpr int NL = 192;      // lanes of waves 1-3
 constexpr int NRS = 8;       // right-hand sides per workgroup
+// kernel variants: any number of right-hand sides; the far band read once for
+// all right-hand sides of a group; exactly one right-hand side
+constexpr int MODE_ANY = 0, MODE_MULTI = 1, MODE_ONE = 2;
 constexpr int NSLOT = 3;     // LDS block slots
 constexpr int BPMAX = 256;   // largest padded half-bandwidth
 
-template <typename T, int CB, int BPC>
+// NTH threads per workgroup: wave 0 runs the critical path, the NL lanes of
+// the other NLW waves load blocks and apply the far band.
+template <typename T, int CB, int BPC, int NTH>
 struct Cfg {
+    static constexpr int NT = NTH;
+    static constexpr int NL = NTH - 64;
+    static constexpr int NLW = NL / 64;
     static constexpr int EL = (CB * (BPC + 1) + NL - 1) / NL;  // L entries per loader lane
     static constexpr int ER = (CB * NRS + NL - 1) / NL;         // right-hand-side values per loader lane
     static constexpr int EPB = EL * NL + CB + 1;                // complex L entries of a slot, columns at stride bp + 2
@@ -55,11 +61,12 @@ struct Cfg {
 };
 
 // LDS carve-up: [NSLOT slots][ring re][ring im][block buffers: forward 2 x Y re/im + P re/im;
-// backward 2 x 3 far-sum partials re/im + B re/im]
+// backward 2 x NLW far-sum partials re/im + B re/im]
 // (masked L reads below read the slot's zero entry instead of branching)
-template <typename T, int CB, int BPC>
+template <typename T, int CB, int BPC, int NTH>
 __host__ __device__ constexpr size_t smem_elems(int bp) {
-    return (size_t)NSLOT * Cfg<T, CB, BPC>::SLOT + 2 * (size_t)(bp + CB) * NRS + 14 * (size_t)CB * NRS;
+    using C = Cfg<T, CB, BPC, NTH>;
+    return (size_t)NSLOT * C::SLOT + 2 * (size_t)(bp + CB) * NRS + (4 * (size_t)C::NLW + 2) * CB * NRS;
 }
 
 // Loader: global -> registers for block blk.  Addresses are clamped into the
@@ -68,7 +75,7 @@ __host__ __device__ constexpr size_t smem_elems(int bp) {
 // Entries outside the block (columns past M_x, rows past M_x, right-hand
 // sides past nrhs, blocks past the end) hold finite copies of valid entries;
 // every use below masks them out.
-template <typename T, int CB, int EL, int ER>
+template <typename T, int CB, int EL, int ER, int NL>
 __device__ __forceinline__ void fetch(cplx<T> (&l)[EL], cplx<T> (&r)[ER], const cplx<T>* base, int blk, int nblk,
                                       int Mx, int bp1, const T* vre, const T* vim, size_t rstride, int nr, int rowoff,
                                       int li) {
@@ -100,7 +107,7 @@ __device__ __forceinline__ void fetch(cplx<T> (&l)[EL], cplx<T> (&r)[ER], const 
 // are bp + 2 apart (entry d of column c at c * (bp + 2) + d), so that lanes
 // reading one row of L across columns hit distinct banks.  Entries past the
 // block's CB columns go to the end of the slot.
-template <int CB, int EL>
+template <int CB, int EL, int NL>
 __device__ __forceinline__ void lds_offsets(int (&off)[EL], int bp1, int li) {
 #pragma unroll
     for (int j = 0; j < EL; ++j) {
@@ -110,7 +117,7 @@ __device__ __forceinline__ void lds_offsets(int (&off)[EL], int bp1, int li) {
 }
 
 // loader: registers -> LDS slot
-template <typename T, int EPB, int ERB, int EL, int ER>
+template <typename T, int EPB, int ERB, int EL, int ER, int NL>
 __device__ __forceinline__ void deposit(const cplx<T> (&l)[EL], const cplx<T> (&r)[ER], const int (&off)[EL],
                                         T* slot, int li) {
     cplx<T>* L = reinterpret_cast<cplx<T>*>(slot);
@@ -130,16 +137,17 @@ __device__ __forceinline__ void deposit(const cplx<T> (&l)[EL], const cplx<T> (&
 
 // Forward, off the critical path (waves 1-3): rows c0 + CB + rr, rr in
 // [CB, bp), of the pending ring take the update by block (c0, nb) with its
-// solution y.  cs = (c0 + CB) mod ring.  With PW = 2 the CB columns of a row
-// are split over the two halves of a wave (lane and lane + 32).
-template <typename T, int CB, int PW>
+// solution y.  cs = (c0 + CB) mod ring.  With PW > 1 the CB columns of a row
+// are split over PW lanes 64 / PW apart in a wave.
+template <typename T, int CB, int PW, int NL>
 __device__ __forceinline__ void forward_far_update(const cplx<T>* L, const T* YR, const T* YI, T* QR, T* QI, int c0,
                                                    int nb, int Mx, int bp, int ls, int nr, int cs, int ring, int zero,
                                                    int li) {
     constexpr int KP = CB / PW;                   // columns per lane
     constexpr int IPP = NL / PW;                  // rows per pass
-    const int part = PW == 1 ? 0 : (li & 63) >> 5;
-    const int slot_item = PW == 1 ? li : (li >> 6) * 32 + (li & 31);
+    constexpr int LPP = 64 / PW;                  // rows per wave and pass
+    const int part = (li & 63) / LPP;
+    const int slot_item = (li >> 6) * LPP + (li & (LPP - 1));
     const int nrow = bp - CB;
     for (int t = 0; t < nr; ++t) {
         for (int m0 = 0; m0 < nrow; m0 += IPP) {
@@ -155,9 +163,10 @@ __device__ __forceinline__ void forward_far_update(const cplx<T>* L, const T* YR
                 const cplx<T> l = L[e];
                 cmac(ar, ai, l.re, l.im, YR[k * NRS + t], YI[k * NRS + t]);
             }
-            if constexpr (PW == 2) {
-                ar += __shfl_xor(ar, 32, 64);
-                ai += __shfl_xor(ai, 32, 64);
+#pragma unroll
+            for (int off = LPP; off < 64; off <<= 1) {
+                ar += __shfl_xor(ar, off, 64);
+                ai += __shfl_xor(ai, off, 64);
             }
             if (row_ok && part == 0) {
                 int s = cs + rr;
@@ -171,14 +180,15 @@ __device__ __forceinline__ void forward_far_update(const cplx<T>* L, const T* YR
 
 // The same for several right-hand sides at once: each L entry is read once
 // and applied to all NRS of them (right-hand sides past nr see zero y).
-template <typename T, int CB, int PW>
+template <typename T, int CB, int PW, int NL>
 __device__ __forceinline__ void forward_far_update_multi(const cplx<T>* L, const T* YR, const T* YI, T* QR, T* QI,
                                                          int c0, int nb, int Mx, int bp, int ls, int nr, int cs,
                                                          int ring, int zero, int li) {
     constexpr int KP = CB / PW;
     constexpr int IPP = NL / PW;
-    const int part = PW == 1 ? 0 : (li & 63) >> 5;
-    const int slot_item = PW == 1 ? li : (li >> 6) * 32 + (li & 31);
+    constexpr int LPP = 64 / PW;                  // rows per wave and pass
+    const int part = (li & 63) / LPP;
+    const int slot_item = (li >> 6) * LPP + (li & (LPP - 1));
     const int nrow = bp - CB;
     for (int m0 = 0; m0 < nrow; m0 += IPP) {
         const int m = m0 + slot_item;
@@ -196,13 +206,13 @@ __device__ __forceinline__ void forward_far_update_multi(const cplx<T>* L, const
 #pragma unroll
             for (int t = 0; t < NRS; ++t) cmac(ar[t], ai[t], l.re, l.im, YR[k * NRS + t], YI[k * NRS + t]);
         }
-        if constexpr (PW == 2) {
 #pragma unroll
-            for (int t = 0; t < NRS; ++t) {
-                ar[t] += __shfl_xor(ar[t], 32, 64);
-                ai[t] += __shfl_xor(ai[t], 32, 64);
+        for (int t = 0; t < NRS; ++t)
+#pragma unroll
+            for (int off = LPP; off < 64; off <<= 1) {
+                ar[t] += __shfl_xor(ar[t], off, 64);
+                ai[t] += __shfl_xor(ai[t], off, 64);
             }
-        }
         if (row_ok && part == 0) {
             int s = cs + rr;
             s = s >= ring ? s - ring : s;
@@ -337,10 +347,10 @@ __device__ __forceinline__ void chain2(T& vr, T& vi, T& ar, T& ai, const cplx<T>
 }  // namespace
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int BPC, bool MULTI>
-__global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp, int nsys,
+template <typename T, int CB, int BPC, int MODE, int NTH>
+__global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp, int nsys,
                                                            int nrhs, const T* __restrict__ G, T* __restrict__ W) {
-    using C = Cfg<T, CB, BPC>;
+    using C = Cfg<T, CB, BPC, NTH>;
     constexpr int GPW = 64 / CB;                  // right-hand sides per chain pass
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
@@ -369,7 +379,7 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
     auto wrap = [ring](int x) { return x >= ring ? x - ring : x; };
 
     // initial window: rows [0, ring); no update of block 0 yet
-    for (int q = tid; q < ring * NRS; q += NT) {
+    for (int q = tid; q < ring * NRS; q += C::NT) {
         const int row = q / NRS, t = q % NRS;
         T re = 0, im = 0;
         if (row < Mx && t < nr) {
@@ -379,16 +389,16 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         QR[q] = re;
         QI[q] = im;
     }
-    for (int q = tid; q < CB * NRS; q += NT) {
+    for (int q = tid; q < CB * NRS; q += C::NT) {
         PR[q] = 0;
         PI[q] = 0;
     }
-    for (int q = tid; q < 2 * CB * NRS; q += NT) {     // right-hand sides past nr stay zero
+    for (int q = tid; q < 2 * CB * NRS; q += C::NT) {     // right-hand sides past nr stay zero
         YR[q] = 0;
         YI[q] = 0;
     }
 
-    for (int q = tid; q < NSLOT; q += NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
+    for (int q = tid; q < NSLOT; q += C::NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
 
     if (wave > 0) {
         // The payload of block b is its L block and the g of the rows
@@ -397,11 +407,11 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         const int li = tid - 64;
         cplx<T> la[C::EL], ra[C::ER], lb[C::EL], rb[C::ER];
         int off[C::EL];
-        lds_offsets<CB, C::EL>(off, bp1, li);
-        fetch<T, CB, C::EL, C::ER>(la, ra, base, 0, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
-        deposit<T, C::EPB, C::ERB, C::EL, C::ER>(la, ra, off, slots, li);
-        fetch<T, CB, C::EL, C::ER>(lb, rb, base, 1, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
-        fetch<T, CB, C::EL, C::ER>(la, ra, base, 2, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
+        lds_offsets<CB, C::EL, C::NL>(off, bp1, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(la, ra, base, 0, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
+        deposit<T, C::EPB, C::ERB, C::EL, C::ER, C::NL>(la, ra, off, slots, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(lb, rb, base, 1, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(la, ra, base, 2, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
         __syncthreads();
         int cs = 0;                               // c0 of the current step, mod ring
         // One step on register set (lx, rx).  The two sets are passed in
@@ -409,8 +419,8 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
         // registers (a choice between them would put them in scratch memory).
         auto step = [&](int s, cplx<T>(&lx)[C::EL], cplx<T>(&rx)[C::ER]) {
             T* dst = slots + ((s + 1) % NSLOT) * C::SLOT;
-            deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lx, rx, off, dst, li);
-            fetch<T, CB, C::EL, C::ER>(lx, rx, base, s + 3, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
+            deposit<T, C::EPB, C::ERB, C::EL, C::ER, C::NL>(lx, rx, off, dst, li);
+            fetch<T, CB, C::EL, C::ER, C::NL>(lx, rx, base, s + 3, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
             {
                 // rows two or more blocks below block s - 1
                 const int i = s - 1;
@@ -419,21 +429,25 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                     const int yo = (i & 1) * CB * NRS;
                     const cplx<T>* L = reinterpret_cast<const cplx<T>*>(LR);
                     const int nbi = min(CB, Mx - i * CB);
-                    const bool pw2 = (bp - CB) * 2 <= NL;
-                    if constexpr (MULTI) {
-                        if (pw2)
-                            forward_far_update_multi<T, CB, 2>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls,
-                                                               nr, cs, ring, C::ZERO, li);
+                    // lanes per row: as many as the rows leave room for
+                    auto far = [&](auto PWc) {
+                        constexpr int PW = decltype(PWc)::value;
+                        if constexpr (MODE == MODE_MULTI)
+                            forward_far_update_multi<T, CB, PW, C::NL>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx,
+                                                                       bp, ls, nr, cs, ring, C::ZERO, li);
                         else
-                            forward_far_update_multi<T, CB, 1>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls,
-                                                               nr, cs, ring, C::ZERO, li);
-                    } else if (pw2) {
-                        forward_far_update<T, CB, 2>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls, nr, cs,
-                                                     ring, C::ZERO, li);
-                    } else {
-                        forward_far_update<T, CB, 1>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp, ls, nr, cs,
-                                                     ring, C::ZERO, li);
-                    }
+                            forward_far_update<T, CB, PW, C::NL>(L, YR + yo, YI + yo, QR, QI, i * CB, nbi, Mx, bp,
+                                                                 ls, nr, cs, ring, C::ZERO, li);
+                    };
+                    // (fixed at compile time where it holds for every bp <= BPC)
+                    if constexpr (CB >= 4 && C::NL >= 4 * (BPC - CB))
+                        far(std::integral_constant<int, 4>{});
+                    else if constexpr (C::NL >= 2 * (BPC - CB))
+                        far(std::integral_constant<int, 2>{});
+                    else if ((bp - CB) * 2 <= C::NL)
+                        far(std::integral_constant<int, 2>{});
+                    else
+                        far(std::integral_constant<int, 1>{});
                 }
             }
             __syncthreads();
@@ -472,7 +486,7 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                     wim[(size_t)t * rstride + c0 + k2] = w.im;
                 }
             };
-            if (nr == 1) {
+            if (MODE == MODE_ONE || nr == 1) {
                 // group 0: row k2 of the unit lower-triangular diagonal block;
                 // group 1: row k2 of the block below (collects -P)
                 cplx<T> l[CB];
@@ -493,7 +507,7 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
                     PR[k2 * NRS] = -vr;
                     PI[k2 * NRS] = -vi;
                 }
-            } else {
+            } else if constexpr (MODE != MODE_ONE) {
                 cplx<T> l[CB], p[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
@@ -528,10 +542,10 @@ __global__ void __launch_bounds__(NT) sweep_forward_kernel(const cplx<T>* __rest
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int BPC, bool MULTI>
-__global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp,
+template <typename T, int CB, int BPC, int MODE, int NTH>
+__global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp,
                                                             int nsys, int nrhs, T* __restrict__ W) {
-    using C = Cfg<T, CB, BPC>;
+    using C = Cfg<T, CB, BPC, NTH>;
     constexpr int GPW = 64 / CB;
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
@@ -540,9 +554,10 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
     T* slots = reinterpret_cast<T*>(smem_raw);
     T* ZR = slots + NSLOT * C::SLOT;              // finished z, ring [ring][NRS]
     T* ZI = ZR + ring * NRS;
-    T* SR = ZI + ring * NRS;                      // far-sum partials, [2][3][CB][NRS] by step parity
-    T* SI = SR + 6 * CB * NRS;
-    T* BR = SI + 6 * CB * NRS;                    // sums over the block just finished, [CB][NRS]
+    constexpr int NP = C::NLW;                    // far-sum partials, one per loader wave
+    T* SR = ZI + ring * NRS;                      // far-sum partials, [2][NP][CB][NRS] by step parity
+    T* SI = SR + 2 * NP * CB * NRS;
+    T* BR = SI + 2 * NP * CB * NRS;               // sums over the block just finished, [CB][NRS]
     T* BI = BR + CB * NRS;
     const int sys = blockIdx.x;
     const int r0 = blockIdx.y * NRS;
@@ -557,21 +572,21 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
     const int nbar = (nblk + 1) & ~1;
     auto wrap = [ring](int x) { return x >= ring ? x - ring : x; };
 
-    for (int q = tid; q < ring * NRS; q += NT) {
+    for (int q = tid; q < ring * NRS; q += C::NT) {
         ZR[q] = 0;
         ZI[q] = 0;
     }
-    for (int q = tid; q < 6 * CB * NRS; q += NT) {
+    for (int q = tid; q < 2 * NP * CB * NRS; q += C::NT) {
         SR[q] = 0;
         SI[q] = 0;
     }
-    for (int q = tid; q < CB * NRS; q += NT) {
+    for (int q = tid; q < CB * NRS; q += C::NT) {
         BR[q] = 0;
         BI[q] = 0;
     }
     const int cs0 = ((nblk - 1) * CB) % ring;     // c0 of the first block processed, mod ring
 
-    for (int q = tid; q < NSLOT; q += NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
+    for (int q = tid; q < NSLOT; q += C::NT) reinterpret_cast<cplx<T>*>(slots + q * C::SLOT)[C::ZERO] = cplx<T>{0, 0};
 
     if (wave > 0) {
         // step s processes block nblk - 1 - s; the payload of a block is its L
@@ -580,29 +595,29 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
         const int li = tid - 64;
         cplx<T> la[C::EL], ra[C::ER], lb[C::EL], rb[C::ER];
         int off[C::EL];
-        lds_offsets<CB, C::EL>(off, bp1, li);
-        fetch<T, CB, C::EL, C::ER>(la, ra, base, nblk - 1, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
-        fetch<T, CB, C::EL, C::ER>(lb, rb, base, nblk - 2, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
-        deposit<T, C::EPB, C::ERB, C::EL, C::ER>(la, ra, off, slots + 0 * C::SLOT, li);
-        deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lb, rb, off, slots + 1 * C::SLOT, li);
-        fetch<T, CB, C::EL, C::ER>(la, ra, base, nblk - 3, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
-        fetch<T, CB, C::EL, C::ER>(lb, rb, base, nblk - 4, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
+        lds_offsets<CB, C::EL, C::NL>(off, bp1, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(la, ra, base, nblk - 1, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(lb, rb, base, nblk - 2, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
+        deposit<T, C::EPB, C::ERB, C::EL, C::ER, C::NL>(la, ra, off, slots + 0 * C::SLOT, li);
+        deposit<T, C::EPB, C::ERB, C::EL, C::ER, C::NL>(lb, rb, off, slots + 1 * C::SLOT, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(la, ra, base, nblk - 3, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
+        fetch<T, CB, C::EL, C::ER, C::NL>(lb, rb, base, nblk - 4, nblk, Mx, bp1, wre, wim, rstride, nr, 0, li);
         __syncthreads();
         int cs = cs0;
         // one step on register set (lx, rx), straight-line calls as in the forward sweep
         auto step = [&](int s, cplx<T>(&lx)[C::EL], cplx<T>(&rx)[C::ER]) {
             T* dst = slots + ((s + 2) % NSLOT) * C::SLOT;
-            deposit<T, C::EPB, C::ERB, C::EL, C::ER>(lx, rx, off, dst, li);
-            fetch<T, CB, C::EL, C::ER>(lx, rx, base, nblk - 1 - (s + 4), nblk, Mx, bp1, wre, wim, rstride, nr, 0,
+            deposit<T, C::EPB, C::ERB, C::EL, C::ER, C::NL>(lx, rx, off, dst, li);
+            fetch<T, CB, C::EL, C::ER, C::NL>(lx, rx, base, nblk - 1 - (s + 4), nblk, Mx, bp1, wre, wim, rstride, nr, 0,
                                        li);
             {
                 // sums over rows two or more blocks below the block of step s + 1
                 const int a = nblk - 2 - s;
                 if (a >= 0) {
                     const T* LR = slots + ((s + 1) % NSLOT) * C::SLOT;
-                    const int so = ((s + 1) & 1) * 3 * CB * NRS;
-                    constexpr int RPC = (BPC - CB + NL / CB - 1) / (NL / CB);
-                    if constexpr (MULTI)
+                    const int so = ((s + 1) & 1) * NP * CB * NRS;
+                    constexpr int RPC = (BPC - CB + C::NL / CB - 1) / (C::NL / CB);
+                    if constexpr (MODE == MODE_MULTI)
                         backward_far_sums_multi<T, CB, RPC>(reinterpret_cast<const cplx<T>*>(LR), ZR, ZI, SR + so,
                                                             SI + so, a * CB, Mx, bp, ls, nr, cs, ring, C::ZERO, li);
                     else
@@ -634,10 +649,20 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
             const cplx<T>* LN = reinterpret_cast<const cplx<T>*>(slots + ((s + 1) % NSLOT) * C::SLOT);
             const T* SWR = slot + 2 * C::EPB;
             const T* SWI = SWR + C::ERB;
-            const T* SRs = SR + (s & 1) * 3 * CB * NRS;   // far sums: three partials
-            const T* SIs = SI + (s & 1) * 3 * CB * NRS;
-            auto far_r = [&](int q) { return SRs[q] + SRs[CB * NRS + q] + SRs[2 * CB * NRS + q]; };
-            auto far_i = [&](int q) { return SIs[q] + SIs[CB * NRS + q] + SIs[2 * CB * NRS + q]; };
+            const T* SRs = SR + (s & 1) * NP * CB * NRS;  // far sums: NP partials
+            const T* SIs = SI + (s & 1) * NP * CB * NRS;
+            auto far_r = [&](int q) {
+                T v = SRs[q];
+#pragma unroll
+                for (int w = 1; w < NP; ++w) v += SRs[w * CB * NRS + q];
+                return v;
+            };
+            auto far_i = [&](int q) {
+                T v = SIs[q];
+#pragma unroll
+                for (int w = 1; w < NP; ++w) v += SIs[w * CB * NRS + q];
+                return v;
+            };
             const int c0 = blk * CB;
             const int nb = min(CB, Mx - c0);
             const int zs = wrap(cs + kp) * NRS;
@@ -649,7 +674,7 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                     wim[(size_t)t * rstride + c0 + kp] = vi;
                 }
             };
-            if (nr == 1) {
+            if (MODE == MODE_ONE || nr == 1) {
                 // group 0: column kp of the diagonal block (rows c0 + k);
                 // group 1: column kp of the block to the left (collects -B)
                 const cplx<T>* src = grp == 0 ? L : LN;
@@ -673,7 +698,7 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
                     BR[kp * NRS] = -vr;
                     BI[kp * NRS] = -vi;
                 }
-            } else {
+            } else if constexpr (MODE != MODE_ONE) {
                 cplx<T> l[CB], p[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
@@ -703,65 +728,70 @@ __global__ void __launch_bounds__(NT) sweep_backward_kernel(const cplx<T>* __res
 }
 
 // ---------------------------------------------------------------------------
-template <typename T, int CB, int BPC, bool MULTI>
+template <typename T, int CB, int BPC, int MODE, int NTH>
 static hipError_t launch_fwd(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
                              hipStream_t st) {
-    const size_t smem = smem_elems<T, CB, BPC>(bp) * sizeof(T);
-    hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, BPC, MULTI>,
+    const size_t smem = smem_elems<T, CB, BPC, NTH>(bp) * sizeof(T);
+    hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, BPC, MODE, NTH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
-    hipLaunchKernelGGL((sweep_forward_kernel<T, CB, BPC, MULTI>), grid, dim3(NT), smem, st,
+    hipLaunchKernelGGL((sweep_forward_kernel<T, CB, BPC, MODE, NTH>), grid, dim3(NTH), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<const T*>(G),
                        static_cast<T*>(W));
     return hipGetLastError();
 }
 
-template <typename T, int CB, int BPC, bool MULTI>
+template <typename T, int CB, int BPC, int MODE, int NTH>
 static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
-    const size_t smem = smem_elems<T, CB, BPC>(bp) * sizeof(T);
-    hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, BPC, MULTI>,
+    const size_t smem = smem_elems<T, CB, BPC, NTH>(bp) * sizeof(T);
+    hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, BPC, MODE, NTH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
-    hipLaunchKernelGGL((sweep_backward_kernel<T, CB, BPC, MULTI>), grid, dim3(NT), smem, st,
+    hipLaunchKernelGGL((sweep_backward_kernel<T, CB, BPC, MODE, NTH>), grid, dim3(NTH), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W));
     return hipGetLastError();
 }
 
-// Block sizes: a block holds near 4100 complex entries (FP32 32 columns for
-// bp <= 128, 16 for bp <= 256; FP64 16 or 8).  With three or more right-hand
-// sides the backward sweep's diagonal chain (work per column proportional to
-// nrhs * CB) bounds it, and its blocks halve for bp <= 128; the forward
-// sweep is then bound by its far update, which smaller blocks make longer.
+// Configurations (block columns CB, threads per workgroup) by precision,
+// band and right-hand-side count, as measured fastest.  A block holds near
+// 4100 complex entries (CB = 32 FP32 / 16 FP64 for bp <= 128, half that for
+// bp <= 256).  One right-hand side has a variant of its own, without the
+// registers of the general chain; in FP32 it runs seven loader waves (two
+// waves on every SIMD, one issuing while the other waits), and so does the
+// forward sweep from five right-hand sides on; the FP64 slots leave LDS room
+// for three.  With three or more right-hand sides the backward sweep's
+// diagonal chain (work per column proportional to nrhs * CB) bounds it and
+// its blocks halve.  From five (forward) and six (backward) right-hand sides
+// on, the far band is read once for all right-hand sides of a group.
 constexpr int MULTI_RHS = 3;
-// From these right-hand-side counts on, the far-band work reads each L entry
-// once for all right-hand sides of a workgroup (kernels built apart, so the
-// one-right-hand-side code keeps its own schedule).
 constexpr int FWD_MULTI_MIN = 5;
 constexpr int BWD_MULTI_MIN = 6;
+
+// general or multi-right-hand-side variant by the right-hand-side count
+template <typename T, int CB, int BPC, int NTH>
+static hipError_t launch_fwd_rhs(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
+                                 hipStream_t st) {
+    return nrhs >= FWD_MULTI_MIN ? launch_fwd<T, CB, BPC, MODE_MULTI, NTH>(LB, Mx, bp, nsys, nrhs, G, W, st)
+                                 : launch_fwd<T, CB, BPC, MODE_ANY, NTH>(LB, Mx, bp, nsys, nrhs, G, W, st);
+}
+
+template <typename T, int CB, int BPC, int NTH>
+static hipError_t launch_bwd_rhs(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
+    return nrhs >= BWD_MULTI_MIN ? launch_bwd<T, CB, BPC, MODE_MULTI, NTH>(LB, Mx, bp, nsys, nrhs, W, st)
+                                 : launch_bwd<T, CB, BPC, MODE_ANY, NTH>(LB, Mx, bp, nsys, nrhs, W, st);
+}
 
 template <typename T>
 size_t sweep_smem(int bp) {
     if constexpr (sizeof(T) == 4)
-        return bp <= 128 ? std::max(smem_elems<T, 32, 128>(bp), smem_elems<T, 16, 128>(bp)) * 4
-                         : smem_elems<T, 16, 256>(bp) * 4;
+        return bp <= 128 ? std::max({smem_elems<T, 32, 128, 512>(bp), smem_elems<T, 16, 128, 512>(bp),
+                                     smem_elems<T, 32, 128, 256>(bp), smem_elems<T, 16, 128, 256>(bp)}) * 4
+                         : smem_elems<T, 16, 256, 256>(bp) * 4;
     else
-        return bp <= 128 ? std::max(smem_elems<T, 16, 128>(bp), smem_elems<T, 8, 128>(bp)) * 8
-                         : smem_elems<T, 8, 256>(bp) * 8;
-}
-
-template <typename T, int CB, int BPC>
-static hipError_t launch_fwd_any(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                                 hipStream_t st) {
-    return nrhs >= FWD_MULTI_MIN ? launch_fwd<T, CB, BPC, true>(LB, Mx, bp, nsys, nrhs, G, W, st)
-                                 : launch_fwd<T, CB, BPC, false>(LB, Mx, bp, nsys, nrhs, G, W, st);
-}
-
-template <typename T, int CB, int BPC>
-static hipError_t launch_bwd_any(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
-    return nrhs >= BWD_MULTI_MIN ? launch_bwd<T, CB, BPC, true>(LB, Mx, bp, nsys, nrhs, W, st)
-                                 : launch_bwd<T, CB, BPC, false>(LB, Mx, bp, nsys, nrhs, W, st);
+        return bp <= 128 ? std::max(smem_elems<T, 16, 128, 256>(bp), smem_elems<T, 8, 128, 256>(bp)) * 8
+                         : smem_elems<T, 8, 256, 256>(bp) * 8;
 }
 
 template <typename T>
@@ -769,11 +799,14 @@ hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrh
                                hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
-        if (bp <= 128) return launch_fwd_any<T, 32, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        return launch_fwd_any<T, 16, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        if (bp <= 128 && nrhs == 1) return launch_fwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        if (bp <= 128 && nrhs < FWD_MULTI_MIN)
+            return launch_fwd<T, 32, 128, MODE_ANY, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        if (bp <= 128) return launch_fwd<T, 16, 128, MODE_MULTI, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        return launch_fwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
     } else {
-        if (bp <= 128) return launch_fwd_any<T, 16, 128>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        return launch_fwd_any<T, 8, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        if (bp <= 128) return launch_fwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+        return launch_fwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
     }
 }
 
@@ -781,13 +814,14 @@ template <typename T>
 hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
-        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_any<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128) return launch_bwd_any<T, 32, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        return launch_bwd_any<T, 16, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128 && nrhs == 1) return launch_bwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128 && nrhs < MULTI_RHS) return launch_bwd_rhs<T, 32, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        return launch_bwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     } else {
-        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_any<T, 8, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128) return launch_bwd_any<T, 16, 128>(LB, Mx, bp, nsys, nrhs, W, st);
-        return launch_bwd_any<T, 8, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_rhs<T, 8, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        return launch_bwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     }
 }
 
