@@ -47,8 +47,8 @@ FP64_STAGES_IN_FP32_FORM = ("fwd1", "back", "resid")
 # size), keyed by the SHA-256 of the kernel's source file: a changed source
 # reports traffic as null until the counters are taken again.
 TRAFFIC = {
-    # band_ldl_reg_kernel, square128_nt256: FETCH 1.0947e6 KiB x 1.9997 + WRITE 2.0809e6 KiB x 1.0
-    ("square128_nt256", "band_ldl"): {"source_sha256": "0d0ef240c31e659ff85bb7a6ecacc01cda09b9829b00105114843cfeb796a484", "bytes_per_launch": 4.4943e9},
+    # band_ldl_reg_kernel, square128_nt256: FETCH 1.155414e6 KiB x 1.9997 + WRITE 2.080695e6 KiB x 1.0
+    ("square128_nt256", "band_ldl"): {"source_sha256": "6ec308c4ae84be260753ccada17ca7a721123f7fa727b3dd8632a0a4a157f067", "bytes_per_launch": 4.4966e9},
 }
 
 WORKLOADS = {
