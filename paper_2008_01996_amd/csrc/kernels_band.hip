@@ -392,32 +392,45 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 // Column block B (columns 16B .. 16B + 15) lies in the trailing window of
 // panels q with q < B <= q + 8; there it sits at position m = B - q - 1.  Its
 // band rows 16B .. 16B + 127 (row blocks B .. B + 7) are eight 16x16 MFMA
-// accumulator tiles; tile ra (row block B + ra) is owned by wave
+// accumulator tiles; tile ra (row block B + ra) is owned by tile wave
 // (B + own_shift(ra)) mod 4, in that wave's slot 0 at positions 0-3 and slot
-// 1 at positions 4-7, and every trailing update accumulates into it directly.
-// The shifts give every wave 9 of the 36 tiles a panel updates (owning whole
-// blocks would give 12, 10, 8 and 6) and spread a block's hand-over over the
-// waves.  Row block B + 8 of the block is only touched by the block's own
-// panel.  When block q becomes the panel the owners of its tiles write them
-// to the LDS panel buffer, move their tile of the block at position 4 down
-// to slot 0 and take the block entering at position 7 (prefetched into
-// registers a panel ahead) into slot 1.  The panel is factored in registers
-// as in the window kernel, written to HBM once, and its rows give the tile
-// operands.
+// 1 at positions 4-7, and the trailing updates accumulate into it directly.
+// The shifts give every tile wave 9 of the 36 tiles a panel updates (owning
+// whole blocks would give 12, 10, 8 and 6) and spread a block's hand-over
+// over the waves.  Row block B + 8 of the block is only touched by the
+// block's own panel.
+//
+// Two roles share every SIMD: waves 0-3 factor the panels (a chain of lane
+// broadcasts, latency-bound vector work), waves 4-7 hold the tiles and run
+// the matrix cores.  Iteration q: the tile waves apply panel q - 1 to block
+// q (its tiles at position 0) and hand block q over to the panel buffer,
+// while the chain waves write panel q - 1 to HBM; after a barrier the chain
+// waves factor panel q while the tile waves apply panel q - 1 to positions
+// 1-7.  The chain waves write the factored diagonal block to PD and the rows
+// below it times D to LD (double-buffered), the tile operands.
 // ---------------------------------------------------------------------------
 constexpr int RPS = 17;                                   // panel buffer row stride (complex)
 
 __device__ __forceinline__ constexpr int own_shift(int ra) {
     return ra == 2 || ra == 3 ? 1 : ra == 5 ? 2 : ra >= 6 ? 3 : 0;
 }
+// The tiles of a block with the same shift r go to one wave: r = 0 {0, 1, 4},
+// 1 {2, 3}, 2 {5}, 3 {6, 7}; a tile's prefetch slot is its index in its group.
+__device__ __forceinline__ constexpr int pf_index(int ra) { return ra == 1 || ra == 3 || ra == 7 ? 1 : ra == 4 ? 2 : 0; }
+__device__ __forceinline__ int group_size(int r) { return r == 0 ? 3 : r == 2 ? 1 : 2; }
+__device__ __forceinline__ int group_tile(int r, int i) {
+    return r == 0 ? (i == 2 ? 4 : i) : r == 1 ? 2 + i : r == 2 ? 5 : 6 + i;
+}
 
-__global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restrict__ LB, int Mx,
+__global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restrict__ LB, int Mx,
                                                            int* __restrict__ flag) {
     using T = float;
     using V4 = vec4<float>::type;
     constexpr int bp = 128, bp1 = 129, NROW = 144;
-    constexpr int EP = (16 * bp1 + 255) / 256;            // write-out entries per thread
-    __shared__ cplx<T> P[NROW * RPS];                     // panel rows p0 + 0..143, 16 columns
+    constexpr int EP = (16 * bp1 + 255) / 256;            // write-out entries per chain thread
+    __shared__ cplx<T> PB[2][NROW * RPS];                 // panel rows p0 + 0..143, 16 columns, by panel parity
+    __shared__ cplx<T> LDB[2][128 * RPS];                 // a panel's rows 16.. times D, by panel parity
+    __shared__ cplx<T> PD[16 * RPS];                      // the factored diagonal block of the last panel
     const int sys = blockIdx.x;
     cplx<T>* base = LB + (size_t)sys * Mx * bp1;
     const int tid = threadIdx.x;
@@ -426,61 +439,134 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
     const int nblk = (Mx + 15) / 16;
     const cplx<T> zero = {T(0), T(0)};
 
-    // tile ra of column block B, this lane's entry j: row 16B + 16 ra + li,
-    // column 16B + 4 lk + j.  Loads are issued raw (clamped address) and
-    // masked where they are used, so that they stay in flight.
-    auto tile_ok = [&](int B, int ra, int j) {
-        return B < nblk && 16 * B + 4 * lk + j < Mx && 16 * ra + li - 4 * lk - j >= 0;
-    };
-    auto tile_load = [&](int B, int ra, cplx<T> (&v)[4]) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = 16 * B + 4 * lk + j;
-            const int d = 16 * ra + li - 4 * lk - j;
-            const cplx<T>* e = base + (tile_ok(B, ra, j) ? (size_t)c * bp1 + d : 0);
-            v[j].re = e->re;
-            v[j].im = e->im;
-        }
-    };
-    // does this wave own tile ra of column block B
-    auto owns = [&](int B, int ra) { return ((B + own_shift(ra)) & 3) == wave; };
-    // row block 8 of column block B: entry (row 128 + tid / 16, column tid % 16)
-    const int r8r = 128 + (tid >> 4), r8c = tid & 15;
-    auto row8_ok = [&](int B) { return B < nblk && 16 * B + r8c < Mx && r8r - r8c <= bp; };
-    auto row8_load = [&](int B) -> cplx<T> {
-        return base[row8_ok(B) ? (size_t)(16 * B + r8c) * bp1 + (r8r - r8c) : 0];
-    };
+    // panel 0 straight into its buffer
+    for (int e = tid; e < NROW * 16; e += 512) {
+        const int r = e >> 4, c = e & 15, d = r - c;
+        const bool ok = c < Mx && d >= 0 && d <= bp;
+        const cplx<T>* x = base + (ok ? (size_t)c * bp1 + d : 0);
+        PB[0][r * RPS + c] = ok ? cplx<T>{x->re, x->im} : zero;
+    }
 
-    V4 accR[2][8], accI[2][8];
-    cplx<T> pf[8][4];
-    {
-        // panel 0 straight into P; blocks 1-8 into the owners' slots
-        for (int e = tid; e < NROW * 16; e += 256) {
-            const int r = e >> 4, c = e & 15, d = r - c;
-            const bool ok = c < Mx && d >= 0 && d <= bp;
-            const cplx<T> x = base[ok ? (size_t)c * bp1 + d : 0];
-            P[r * RPS + c] = ok ? x : zero;
-        }
+    if (wave >= 4) {
+        // ================= tile waves =================
+        const int tw = wave - 4, ttid = tid - 256;
+        // tile ra of column block B, this lane's entry j: row 16B + 16 ra + li,
+        // column 16B + 4 lk + j.  Loads are issued raw (clamped address) and
+        // masked where they are used, so that they stay in flight.
+        auto tile_ok = [&](int B, int ra, int j) {
+            return B < nblk && 16 * B + 4 * lk + j < Mx && 16 * ra + li - 4 * lk - j >= 0;
+        };
+        auto tile_load = [&](int B, int ra, cplx<T> (&v)[4]) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = 16 * B + 4 * lk + j;
+                const int d = 16 * ra + li - 4 * lk - j;
+                const cplx<T>* e = base + (tile_ok(B, ra, j) ? (size_t)c * bp1 + d : 0);
+                v[j].re = e->re;
+                v[j].im = e->im;
+            }
+        };
+        auto owns = [&](int B, int ra) { return ((B + own_shift(ra)) & 3) == tw; };
+        // row block 8 of column block B: entry (row 128 + ttid / 16, column ttid % 16)
+        const int r8r = 128 + (ttid >> 4), r8c = ttid & 15;
+        auto row8_ok = [&](int B) { return B < nblk && 16 * B + r8c < Mx && r8r - r8c <= bp; };
+        auto row8_load = [&](int B) -> cplx<T> {
+            const cplx<T>* e = base + (row8_ok(B) ? (size_t)(16 * B + r8c) * bp1 + (r8r - r8c) : 0);
+            return cplx<T>{e->re, e->im};
+        };
+        // C -= L_c D L_r^T on a tile: the columns are rows 16 m + li of the
+        // previous panel's rows 16.. (m the block's position), the rows rows
+        // 16 (m + ra) + li; operands from that panel's buffer Pp and its LD
+        auto tile_mfma = [&](V4& cr, V4& ci, const cplx<T>* Pp, const cplx<T>* LD, int m, int ra) {
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const cplx<T> x = Pp[(16 + 16 * m + li) * RPS + k], y = LD[(16 * (m + ra) + li) * RPS + k];
+                cr = mfma16x16x4<T>(-x.re, y.re, cr);
+                ci = mfma16x16x4<T>(-x.re, y.im, ci);
+                cr = mfma16x16x4<T>(x.im, y.im, cr);
+                ci = mfma16x16x4<T>(-x.im, y.re, ci);
+            }
+        };
+
+        V4 accR[2][8], accI[2][8];
+        cplx<T> pf[3][4];                                 // the owned tiles of the next entering block
+        // prefetch this wave's tiles of block B into pf
+        auto prefetch = [&](int B) {
+            const int r = (tw - B) & 3;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                if (i < group_size(r)) tile_load(B, group_tile(r, i), pf[i]);
+        };
 #pragma unroll
         for (int ra = 0; ra < 8; ++ra) {
-            int b0 = (wave - own_shift(ra)) & 3;         // this wave's blocks of tile ra: b0, b0 + 4
+            int b0 = (tw - own_shift(ra)) & 3;            // this wave's blocks of tile ra: b0, b0 + 4
             b0 = b0 == 0 ? 4 : b0;
 #pragma unroll
             for (int sl = 0; sl < 2; ++sl) {
-                tile_load(b0 + 4 * sl, ra, pf[ra]);
+                cplx<T> v[4];
+                tile_load(b0 + 4 * sl, ra, v);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const bool ok = tile_ok(b0 + 4 * sl, ra, j);
-                    accR[sl][ra][j] = ok ? pf[ra][j].re : T(0);
-                    accI[sl][ra][j] = ok ? pf[ra][j].im : T(0);
+                    accR[sl][ra][j] = ok ? v[j].re : T(0);
+                    accI[sl][ra][j] = ok ? v[j].im : T(0);
                 }
             }
         }
-    }
+        prefetch(9);
+        cplx<T> r8 = row8_load(1);
+        __syncthreads();
+
+        for (int q = 0; q < nblk; ++q) {
+            cplx<T>* P = PB[q & 1];
+            const cplx<T>* Pp = PB[(q + 1) & 1];           // panel q - 1
+            const cplx<T>* LD = LDB[(q + 1) & 1];
+            if (q > 0) {
+                // ---- panel q - 1 on block q (position 0), then hand-over: the
+                // tiles of block q into P; the block at position 4 moves to
+                // slot 0, block q + 8 enters slot 1
 #pragma unroll
-    for (int ra = 0; ra < 8; ++ra)
-        if (owns(9, ra)) tile_load(9, ra, pf[ra]);
-    cplx<T> r8 = row8_load(1);
+                for (int ra = 0; ra < 8; ++ra) {
+                    if (owns(q, ra)) {
+                        tile_mfma(accR[0][ra], accI[0][ra], Pp, LD, 0, ra);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            P[(16 * ra + li) * RPS + 4 * lk + j] = cplx<T>{accR[0][ra][j], accI[0][ra][j]};
+                        accR[0][ra] = accR[1][ra];
+                        accI[0][ra] = accI[1][ra];
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const bool ok = tile_ok(q + 8, ra, j);
+                            accR[1][ra][j] = ok ? pf[pf_index(ra)][j].re : T(0);
+                            accI[1][ra][j] = ok ? pf[pf_index(ra)][j].im : T(0);
+                        }
+                    }
+                }
+                P[r8r * RPS + r8c] = row8_ok(q) ? r8 : zero;
+                prefetch(q + 9);                          // for the next hand-over
+                r8 = row8_load(q + 1);
+            }
+            __syncthreads();
+            // ---- panel q - 1 on positions 1-7 (block q + m at position m: slot m > 4)
+            if (q > 0) {
+#pragma unroll
+                for (int m = 1; m < 8; ++m) {
+                    if (q + m < nblk) {
+#pragma unroll
+                        for (int ra = 0; ra < 8 - m; ++ra) {
+                            if (!owns(q + m, ra)) continue;
+                            tile_mfma(accR[m > 4][ra], accI[m > 4][ra], Pp, LD, m, ra);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        return;
+    }
+
+    // ================= chain waves =================
     int ecol[EP], erow[EP];
 #pragma unroll
     for (int j = 0; j < EP; ++j) {
@@ -488,123 +574,79 @@ __global__ void __launch_bounds__(256) band_ldl_reg_kernel(cplx<float>* __restri
         ecol[j] = e / bp1;
         erow[j] = e - ecol[j] * bp1 + ecol[j];            // panel row of band entry (column, d)
     }
+    // finished panel q to HBM: rows of the diagonal block from PD, the others from P
+    auto write_out = [&](int q) {
+        const cplx<T>* P = PB[q & 1];
+        cplx<T>* dst = base + (size_t)16 * q * bp1;
+        const int nb = min(16, Mx - 16 * q);
+#pragma unroll
+        for (int j = 0; j < EP; ++j) {
+            const int e = tid + 256 * j;
+            if (e < 16 * bp1 && ecol[j] < nb) {
+                const cplx<T>* src = erow[j] < 16 ? PD + erow[j] * RPS + ecol[j] : P + erow[j] * RPS + ecol[j];
+                dst[e] = cplx<T>{src->re, src->im};
+            }
+        }
+    };
+    const bool own = lane < 48;
+    const int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
     __syncthreads();
 
     for (int q = 0; q < nblk; ++q) {
-        const int p0 = 16 * q;
-        const int nb = min(16, Mx - p0);
-        if (q > 0) {
-            // ---- hand over: the tiles of block q from their owners' slot 0
-            // into P; the block at position 4 moves to slot 0, block q + 8
-            // enters slot 1
-#pragma unroll
-            for (int ra = 0; ra < 8; ++ra) {
-                if (owns(q, ra)) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        P[(16 * ra + li) * RPS + 4 * lk + j] = cplx<T>{accR[0][ra][j], accI[0][ra][j]};
-                    accR[0][ra] = accR[1][ra];
-                    accI[0][ra] = accI[1][ra];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const bool ok = tile_ok(q + 8, ra, j);
-                        accR[1][ra][j] = ok ? pf[ra][j].re : T(0);
-                        accI[1][ra][j] = ok ? pf[ra][j].im : T(0);
-                    }
-                }
-            }
-            P[r8r * RPS + r8c] = row8_ok(q) ? r8 : zero;
-            // prefetch for panel q + 1
-#pragma unroll
-            for (int ra = 0; ra < 8; ++ra)
-                if (owns(q + 9, ra)) tile_load(q + 9, ra, pf[ra]);
-            r8 = row8_load(q + 1);
-        }
+        cplx<T>* P = PB[q & 1];
+        cplx<T>* LD = LDB[q & 1];
+        const int nb = min(16, Mx - 16 * q);
+        if (q > 0) write_out(q - 1);
         __syncthreads();
-        // ---- factor the panel in registers (one row per lane: lanes 0-15 the
+        // ---- factor panel q in registers (one row per lane: lanes 0-15 the
         // diagonal block in every wave, lanes 16-47 of wave w rows 16 + 32 w ..)
-        {
-            const bool own = lane < 48;
-            const int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
-            cplx<T> a[16];
+        cplx<T> a[16];
 #pragma unroll
-            for (int c = 0; c < 16; ++c) a[c] = P[(own ? rrel : 0) * RPS + c];
+        for (int c = 0; c < 16; ++c) {
+            const cplx<T>* e = P + (own ? rrel : 0) * RPS + c;
+            a[c] = cplx<T>{e->re, e->im};
+        }
+        int bad = 0;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                if (k < nb) {
-                    const cplx<T> dk = {lane_bcast(a[k].re, k), lane_bcast(a[k].im, k)};
-                    const cplx<T> inv = cinv_fast(dk);
-                    if (tid == 0) {
-                        const T mag = fabs(dk.re) + fabs(dk.im);
-                        if (!(mag > T(0)) || !isfinite(mag)) atomicOr(flag, 1);
-                    }
-                    const cplx<T> aik = a[k];
-                    if (rrel > k) a[k] = cmul(aik, inv);
+        for (int k = 0; k < 16; ++k) {
+            if (k < nb) {
+                const cplx<T> dk = {lane_bcast(a[k].re, k), lane_bcast(a[k].im, k)};
+                const cplx<T> inv = cinv_fast(dk);
+                const T mag = fabs(dk.re) + fabs(dk.im);
+                bad |= int(!(mag > T(0))) | int(!isfinite(mag));
+                const cplx<T> aik = a[k];
+                if (rrel > k) a[k] = cmul(aik, inv);
 #pragma unroll
-                    for (int j = k + 1; j < 16; ++j) {
-                        const T lr = lane_bcast(a[k].re, j), lim = lane_bcast(a[k].im, j);
-                        a[j].re = fma(-aik.re, lr, a[j].re);
-                        a[j].re = fma(aik.im, lim, a[j].re);
-                        a[j].im = fma(-aik.re, lim, a[j].im);
-                        a[j].im = fma(-aik.im, lr, a[j].im);
-                    }
+                for (int j = k + 1; j < 16; ++j) {
+                    const T lr = lane_bcast(a[k].re, j), lim = lane_bcast(a[k].im, j);
+                    a[j].re = fma(-aik.re, lr, a[j].re);
+                    a[j].re = fma(aik.im, lim, a[j].re);
+                    a[j].im = fma(-aik.re, lim, a[j].im);
+                    a[j].im = fma(-aik.im, lr, a[j].im);
                 }
-                __builtin_amdgcn_sched_barrier(0);
             }
-            const bool writer = own && (lane >= 16 || wave == 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (tid == 0 && bad != 0) atomicOr(flag, 1);
+        // the diagonal entries D_c of this panel, from the diagonal lanes
+        cplx<T> dc[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) dc[c] = cplx<T>{lane_bcast(a[c].re, c), lane_bcast(a[c].im, c)};
+        if (own && lane >= 16) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                P[rrel * RPS + c] = a[c];
+                LD[(rrel - 16) * RPS + c] = cmul(a[c], dc[c]);
+            }
+        }
+        if (wave == 0 && lane < 16) {
 #pragma unroll
             for (int c = 0; c < 16; ++c)
-                if (writer && c <= rrel) P[rrel * RPS + c] = a[c];
-        }
-        __syncthreads();
-        // ---- finished panel to HBM
-        {
-            cplx<T>* dst = base + (size_t)p0 * bp1;
-#pragma unroll
-            for (int j = 0; j < EP; ++j) {
-                const int e = tid + 256 * j;
-                if (e < 16 * bp1 && ecol[j] < nb) dst[e] = P[erow[j] * RPS + ecol[j]];
-            }
-        }
-        // ---- trailing update into the owners' accumulator tiles.  Operands:
-        // lo[m][kk] = L[p0 + 16 + 16 m + li, p0 + 4 kk + lk], ld = lo * D.
-        // Tile (row block q + 1 + m + ra, column block q + 1 + m):
-        //   C[c', r] -= sum_k L[c', k] D_k L[r, k].
-        {
-            cplx<T> lo[8][4], ld[8][4];
-#pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const int k = 4 * kk + lk;
-                const cplx<T> dk = P[k * RPS + k];
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    lo[m][kk] = P[(16 + 16 * m + li) * RPS + k];
-                    ld[m][kk] = cmul(lo[m][kk], dk);
-                }
-            }
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                if (q + 1 + m < nblk) {
-#pragma unroll
-                    for (int ra = 0; ra < 8 - m; ++ra) {
-                        if (!owns(q + 1 + m, ra)) continue;
-                        V4 cr = accR[m >= 4][ra], ci = accI[m >= 4][ra];
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk) {
-                            const cplx<T> x = lo[m][kk], y = ld[m + ra][kk];
-                            cr = mfma16x16x4<T>(-x.re, y.re, cr);
-                            cr = mfma16x16x4<T>(x.im, y.im, cr);
-                            ci = mfma16x16x4<T>(-x.re, y.im, ci);
-                            ci = mfma16x16x4<T>(-x.im, y.re, ci);
-                        }
-                        accR[m >= 4][ra] = cr;
-                        accI[m >= 4][ra] = ci;
-                    }
-                }
-            }
+                if (c <= lane) PD[lane * RPS + c] = a[c];
         }
         __syncthreads();
     }
+    write_out(nblk - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -635,7 +677,7 @@ hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStr
     const size_t smem = band_ldl_smem<T>(bp);
     if constexpr (sizeof(T) == 4) {
         if (bp == 128) {
-            hipLaunchKernelGGL(band_ldl_reg_kernel, dim3(nsys), dim3(256), 0, st, static_cast<cplx<float>*>(LB), Mx,
+            hipLaunchKernelGGL(band_ldl_reg_kernel, dim3(nsys), dim3(512), 0, st, static_cast<cplx<float>*>(LB), Mx,
                                flag);
             return hipGetLastError();
         }
