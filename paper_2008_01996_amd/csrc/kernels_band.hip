@@ -393,11 +393,11 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 // panels q with q < B <= q + 8; there it sits at position m = B - q - 1.  Its
 // band rows 16B .. 16B + 127 (row blocks B .. B + 7) are eight 16x16 MFMA
 // accumulator tiles; tile ra (row block B + ra) is owned by tile wave
-// (B + own_shift(ra)) mod 4, in that wave's slot 0 at positions 0-3 and slot
-// 1 at positions 4-7, and the trailing updates accumulate into it directly.
-// The shifts give every tile wave 9 of the 36 tiles a panel updates (owning
-// whole blocks would give 12, 10, 8 and 6) and spread a block's hand-over
-// over the waves.  Row block B + 8 of the block is only touched by the
+// (B + ra / 2) mod 4, in that wave's slot 0 at positions 0-3 and slot 1 at
+// positions 4-7, and the trailing updates accumulate into it directly.  The
+// shifts give every tile wave 9 of the 36 tiles a panel updates (owning
+// whole blocks would give 12, 10, 8 and 6) and two tiles of every block, so
+// that the update of the next block and its hand-over are spread evenly.  Row block B + 8 of the block is only touched by the
 // block's own panel.
 //
 // Two roles share every SIMD: waves 0-3 factor the panels (a chain of lane
@@ -411,16 +411,9 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 // ---------------------------------------------------------------------------
 constexpr int RPS = 17;                                   // panel buffer row stride (complex)
 
-__device__ __forceinline__ constexpr int own_shift(int ra) {
-    return ra == 2 || ra == 3 ? 1 : ra == 5 ? 2 : ra >= 6 ? 3 : 0;
-}
-// The tiles of a block with the same shift r go to one wave: r = 0 {0, 1, 4},
-// 1 {2, 3}, 2 {5}, 3 {6, 7}; a tile's prefetch slot is its index in its group.
-__device__ __forceinline__ constexpr int pf_index(int ra) { return ra == 1 || ra == 3 || ra == 7 ? 1 : ra == 4 ? 2 : 0; }
-__device__ __forceinline__ int group_size(int r) { return r == 0 ? 3 : r == 2 ? 1 : 2; }
-__device__ __forceinline__ int group_tile(int r, int i) {
-    return r == 0 ? (i == 2 ? 4 : i) : r == 1 ? 2 + i : r == 2 ? 5 : 6 + i;
-}
+__device__ __forceinline__ constexpr int own_shift(int ra) { return ra >> 1; }
+// The tiles 2r and 2r + 1 of a block go to one wave; a tile's prefetch slot
+// is ra mod 2.
 
 __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restrict__ LB, int Mx,
                                                            int* __restrict__ flag) {
@@ -490,13 +483,12 @@ __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restri
         };
 
         V4 accR[2][8], accI[2][8];
-        cplx<T> pf[3][4];                                 // the owned tiles of the next entering block
-        // prefetch this wave's tiles of block B into pf
+        cplx<T> pf[2][4];                                 // the owned tiles of the next entering block
+        // prefetch this wave's tiles of block B (tiles 2r, 2r + 1) into pf
         auto prefetch = [&](int B) {
             const int r = (tw - B) & 3;
 #pragma unroll
-            for (int i = 0; i < 3; ++i)
-                if (i < group_size(r)) tile_load(B, group_tile(r, i), pf[i]);
+            for (int i = 0; i < 2; ++i) tile_load(B, 2 * r + i, pf[i]);
         };
 #pragma unroll
         for (int ra = 0; ra < 8; ++ra) {
@@ -538,8 +530,8 @@ __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restri
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             const bool ok = tile_ok(q + 8, ra, j);
-                            accR[1][ra][j] = ok ? pf[pf_index(ra)][j].re : T(0);
-                            accI[1][ra][j] = ok ? pf[pf_index(ra)][j].im : T(0);
+                            accR[1][ra][j] = ok ? pf[ra & 1][j].re : T(0);
+                            accI[1][ra][j] = ok ? pf[ra & 1][j].im : T(0);
                         }
                     }
                 }
