@@ -352,6 +352,10 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
                                                            int nrhs, const T* __restrict__ G, T* __restrict__ W) {
     using C = Cfg<T, CB, BPC, NTH>;
     constexpr int GPW = 64 / CB;                  // right-hand sides per chain pass
+    // who copies the rows entering the pending window into the ring: the
+    // loaders, a step after the block, where that measured faster (FP32 with
+    // several right-hand sides; needs bp >= CB), else wave 0 at the block's end
+    constexpr bool LOADER_ENTER = sizeof(T) == 4 && MODE != MODE_ONE;
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
     const int ls = bp + 2;                        // LDS column stride of L
@@ -421,6 +425,20 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
             T* dst = slots + ((s + 1) % NSLOT) * C::SLOT;
             deposit<T, C::EPB, C::ERB, C::EL, C::ER, C::NL>(lx, rx, off, dst, li);
             fetch<T, CB, C::EL, C::ER, C::NL>(lx, rx, base, s + 3, nblk, Mx, bp1, gre, gim, rstride, nr, ring, li);
+            if (LOADER_ENTER && bp >= CB && s >= 1 && s <= nblk) {
+                // the rows entering the window after block s - 1 take the
+                // ring slots of its rows (first read by the far update of
+                // block s, next step; with bp < CB some of them belong to
+                // block s itself, and wave 0 copies them in step s - 1)
+                const T* SGR = slots + ((s - 1) % NSLOT) * C::SLOT + 2 * C::EPB;
+                const T* SGI = SGR + C::ERB;
+                const int csp = cs >= CB ? cs - CB : cs - CB + ring;
+                for (int q = li; q < CB * NRS; q += C::NL) {
+                    const int sl = wrap(csp + q / NRS) * NRS + q % NRS;
+                    QR[sl] = SGR[q];
+                    QI[sl] = SGI[q];
+                }
+            }
             {
                 // rows two or more blocks below block s - 1
                 const int i = s - 1;
@@ -528,12 +546,14 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
                     }
                 }
             }
-            wave_lds_sync();
-            // rows entering the window take the slots of the block's rows
-            for (int q = lane; q < CB * NRS; q += 64) {
-                const int sl = wrap(cs + q / NRS) * NRS + q % NRS;
-                QR[sl] = SGR[q];
-                QI[sl] = SGI[q];
+            if (!LOADER_ENTER || bp < CB) {
+                // the rows entering the window take the slots of the block's rows
+                wave_lds_sync();
+                for (int q = lane; q < CB * NRS; q += 64) {
+                    const int sl = wrap(cs + q / NRS) * NRS + q % NRS;
+                    QR[sl] = SGR[q];
+                    QI[sl] = SGI[q];
+                }
             }
         }
         __syncthreads();
