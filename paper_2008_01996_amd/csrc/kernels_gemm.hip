@@ -146,27 +146,58 @@ size_t gemm_resid_partials(int M, int N, int batch) {
 // Spatial operator for the residual: P[:, j] = M_x U[:, j] and
 // P[:, N_t + j] = A_x U[:, j] (CSR, FP64), for every RHS.
 // ---------------------------------------------------------------------------
+// P = [M_x U | A_x U] per right-hand side.  A thread takes one row and KC
+// time columns: the row's CSR entries (up to NNZ of them in registers, a
+// longer row loops over the rest) are read once and serve both products;
+// for a fixed time column the lanes of a wave read consecutive rows of U.
+constexpr int SPATIAL_KC = 16;
+
+template <int NNZ>
 __global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, const int* __restrict__ rowptr,
                                                             const int* __restrict__ col,
                                                             const double* __restrict__ valM,
                                                             const double* __restrict__ valA,
                                                             const double* __restrict__ U, double* __restrict__ P) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int j = blockIdx.y;             // 0..2 Nt-1
+    const int k0 = blockIdx.y * SPATIAL_KC;
     const int batch = blockIdx.z;
     if (i >= Mx) return;
-    const int k = j < Nt ? j : j - Nt;
-    const double* val = j < Nt ? valM : valA;
-    const double* u = U + (size_t)batch * Mx * Nt + (size_t)k * Mx;
-    double s = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) s += val[e] * u[col[e]];
-    P[(size_t)batch * Mx * 2 * Nt + (size_t)j * Mx + i] = s;
+    const int e0 = rowptr[i], n = rowptr[i + 1] - e0;
+    int c[NNZ];
+    double vm[NNZ], va[NNZ];
+#pragma unroll
+    for (int e = 0; e < NNZ; ++e) {
+        const bool on = e < n;
+        c[e] = on ? col[e0 + e] : i;
+        vm[e] = on ? valM[e0 + e] : 0.0;
+        va[e] = on ? valA[e0 + e] : 0.0;
+    }
+    const double* u = U + (size_t)batch * Mx * Nt;
+    double* pb = P + (size_t)batch * Mx * 2 * Nt;
+    const int k1 = min(k0 + SPATIAL_KC, Nt);
+    for (int k = k0; k < k1; ++k) {
+        const double* uk = u + (size_t)k * Mx;
+        double sm = 0.0, sa = 0.0;
+#pragma unroll
+        for (int e = 0; e < NNZ; ++e) {
+            const double x = uk[c[e]];
+            sm += vm[e] * x;
+            sa += va[e] * x;
+        }
+        for (int e = NNZ; e < n; ++e) {
+            const double x = uk[col[e0 + e]];
+            sm += valM[e0 + e] * x;
+            sa += valA[e0 + e] * x;
+        }
+        pb[(size_t)k * Mx + i] = sm;
+        pb[(size_t)(Nt + k) * Mx + i] = sa;
+    }
 }
 
 hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, const int* col, const double* valM,
                                 const double* valA, const double* U, double* P, hipStream_t st) {
-    dim3 grid((Mx + 255) / 256, 2 * Nt, nrhs);
-    hipLaunchKernelGGL(spatial_apply_kernel, grid, dim3(256), 0, st, Mx, Nt, rowptr, col, valM, valA, U, P);
+    dim3 grid((Mx + 255) / 256, (Nt + SPATIAL_KC - 1) / SPATIAL_KC, nrhs);
+    hipLaunchKernelGGL(spatial_apply_kernel<8>, grid, dim3(256), 0, st, Mx, Nt, rowptr, col, valM, valA, U, P);
     return hipGetLastError();
 }
 
