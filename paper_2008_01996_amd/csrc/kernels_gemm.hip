@@ -40,26 +40,29 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = zero4<TC>();
 
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-        // A tile: 64 rows (m) x 16 (k), coalesced along m
+    // global -> registers for the K step at k0 (A coalesced along m, B along
+    // n); the next step's loads are in flight while this one computes
+    TC ra[4], rb[4];
+    auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = tid & 63, k = (tid >> 6) + 4 * i;
             const int gm = m0 + m, gk = k0 + k;
-            TC v = TC(0);
-            if (gm < g.M && gk < g.K) v = static_cast<TC>(A[(size_t)gm + (size_t)gk * g.lda]);
-            As[k][m] = v;
+            ra[i] = gm < g.M && gk < g.K ? static_cast<TC>(A[(size_t)gm + (size_t)gk * g.lda]) : TC(0);
+            const int gn = n0 + m;
+            rb[i] = gn < g.N && gk < g.K ? B[(size_t)gk * g.ldb + gn] : TC(0);
         }
-        // B tile: 16 (k) x 64 (n), coalesced along n
+    };
+    load(0);
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int n = tid & 63, k = (tid >> 6) + 4 * i;
-            const int gn = n0 + n, gk = k0 + k;
-            TC v = TC(0);
-            if (gn < g.N && gk < g.K) v = B[(size_t)gk * g.ldb + gn];
-            Bs[k][n] = v;
+            const int m = tid & 63, k = (tid >> 6) + 4 * i;
+            As[k][m] = ra[i];
+            Bs[k][m] = rb[i];
         }
         __syncthreads();
+        if (k0 + BK < g.K) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
             const int k = 4 * kk + lk;
