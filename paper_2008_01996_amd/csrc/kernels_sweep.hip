@@ -39,8 +39,9 @@ namespace {
 
 constexpr int NRS = 8;       // right-hand sides per workgroup
 // kernel variants: any number of right-hand sides; the far band read once for
-// all right-hand sides of a group; exactly one right-hand side
-constexpr int MODE_ANY = 0, MODE_MULTI = 1, MODE_ONE = 2;
+// all right-hand sides of a group; exactly one right-hand side; exactly one
+// right-hand side and bp = BPC (every LDS offset a compile-time constant)
+constexpr int MODE_ANY = 0, MODE_MULTI = 1, MODE_ONE = 2, MODE_ONE_EXACT = 3;
 constexpr int NSLOT = 3;     // LDS block slots
 constexpr int BPMAX = 256;   // largest padded half-bandwidth
 
@@ -348,14 +349,17 @@ __device__ __forceinline__ void chain2(T& vr, T& vi, T& ar, T& ai, const cplx<T>
 
 // ---------------------------------------------------------------------------
 template <typename T, int CB, int BPC, int MODE, int NTH>
-__global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp, int nsys,
-                                                           int nrhs, const T* __restrict__ G, T* __restrict__ W) {
+__global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp_in,
+                                                           int nsys, int nrhs, const T* __restrict__ G,
+                                                           T* __restrict__ W) {
     using C = Cfg<T, CB, BPC, NTH>;
+    constexpr bool ONE = MODE == MODE_ONE || MODE == MODE_ONE_EXACT;
+    const int bp = MODE == MODE_ONE_EXACT ? BPC : bp_in;
     constexpr int GPW = 64 / CB;                  // right-hand sides per chain pass
     // who copies the rows entering the pending window into the ring: the
     // loaders, a step after the block, where that measured faster (FP32 with
     // several right-hand sides; needs bp >= CB), else wave 0 at the block's end
-    constexpr bool LOADER_ENTER = sizeof(T) == 4 && MODE != MODE_ONE;
+    constexpr bool LOADER_ENTER = sizeof(T) == 4 && !ONE;
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
     const int ls = bp + 2;                        // LDS column stride of L
@@ -504,7 +508,7 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
                     wim[(size_t)t * rstride + c0 + k2] = w.im;
                 }
             };
-            if (MODE == MODE_ONE || nr == 1) {
+            if (ONE || nr == 1) {
                 // group 0: row k2 of the unit lower-triangular diagonal block;
                 // group 1: row k2 of the block below (collects -P)
                 cplx<T> l[CB];
@@ -525,7 +529,7 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
                     PR[k2 * NRS] = -vr;
                     PI[k2 * NRS] = -vi;
                 }
-            } else if constexpr (MODE != MODE_ONE) {
+            } else if constexpr (!ONE) {
                 cplx<T> l[CB], p[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
@@ -563,9 +567,11 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
 
 // ---------------------------------------------------------------------------
 template <typename T, int CB, int BPC, int MODE, int NTH>
-__global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp,
+__global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp_in,
                                                             int nsys, int nrhs, T* __restrict__ W) {
     using C = Cfg<T, CB, BPC, NTH>;
+    constexpr bool ONE = MODE == MODE_ONE || MODE == MODE_ONE_EXACT;
+    const int bp = MODE == MODE_ONE_EXACT ? BPC : bp_in;
     constexpr int GPW = 64 / CB;
     extern __shared__ unsigned char smem_raw[];
     const int bp1 = bp + 1;
@@ -694,7 +700,7 @@ __global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __re
                     wim[(size_t)t * rstride + c0 + kp] = vi;
                 }
             };
-            if (MODE == MODE_ONE || nr == 1) {
+            if (ONE || nr == 1) {
                 // group 0: column kp of the diagonal block (rows c0 + k);
                 // group 1: column kp of the block to the left (collects -B)
                 const cplx<T>* src = grp == 0 ? L : LN;
@@ -718,7 +724,7 @@ __global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __re
                     BR[kp * NRS] = -vr;
                     BI[kp * NRS] = -vi;
                 }
-            } else if constexpr (MODE != MODE_ONE) {
+            } else if constexpr (!ONE) {
                 cplx<T> l[CB], p[CB];
 #pragma unroll
                 for (int k = 0; k < CB; ++k) {
@@ -819,6 +825,8 @@ hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrh
                                hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
+        if (bp == 128 && nrhs == 1)
+            return launch_fwd<T, 32, 128, MODE_ONE_EXACT, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
         if (bp <= 128 && nrhs == 1) return launch_fwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
         if (bp <= 128 && nrhs < FWD_MULTI_MIN)
             return launch_fwd<T, 32, 128, MODE_ANY, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
@@ -835,6 +843,8 @@ template <typename T>
 hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
     if (bp > BPMAX) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
+        if (bp == 128 && nrhs == 1)
+            return launch_bwd<T, 32, 128, MODE_ONE_EXACT, 512>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128 && nrhs == 1) return launch_bwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128 && nrhs < MULTI_RHS) return launch_bwd_rhs<T, 32, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);

@@ -119,12 +119,13 @@ def test_wide_bands(precision, ncx, ncy, nrhs):
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 
-# Right-hand-side counts that take every sweep variant (one; five and six,
-# where the far-band work switches to reading L once for all right-hand
-# sides; eight, a full group; nine, a full group and a group of one) on
-# meshes of padded half-bandwidth 16, 128 and 256.
-SWEEP_CASES = [(9, 9, 1), (9, 9, 6), (120, 3, 5), (120, 3, 9), (250, 3, 8)]
-SWEEP_IDS = ["sq9_rhs1", "sq9_rhs6", "band120_rhs5", "band120_rhs9", "band250_rhs8"]
+# Right-hand-side counts that take every sweep variant (one, on a narrow band
+# and on padded half-bandwidth 128, where it has a variant of its own; five
+# and six, where the far-band work switches to reading L once for all
+# right-hand sides; eight, a full group; nine, a full group and a group of
+# one) on meshes of padded half-bandwidth 16, 128 and 256.
+SWEEP_CASES = [(9, 9, 1), (9, 9, 6), (120, 3, 1), (120, 3, 5), (120, 3, 9), (250, 3, 8)]
+SWEEP_IDS = ["sq9_rhs1", "sq9_rhs6", "band120_rhs1", "band120_rhs5", "band120_rhs9", "band250_rhs8"]
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
 
 
