@@ -833,6 +833,8 @@ hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrh
         if (bp <= 128) return launch_fwd<T, 16, 128, MODE_MULTI, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
         return launch_fwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
     } else {
+        if (bp == 128 && nrhs == 1)
+            return launch_fwd<T, 16, 128, MODE_ONE_EXACT, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
         if (bp <= 128 && nrhs == 1) return launch_fwd<T, 16, 128, MODE_ONE, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
         if (bp <= 128) return launch_fwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
         return launch_fwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
@@ -851,6 +853,8 @@ hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nr
         return launch_bwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st);
     } else {
         if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_rhs<T, 8, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp == 128 && nrhs == 1)
+            return launch_bwd<T, 16, 128, MODE_ONE_EXACT, 256>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128 && nrhs == 1) return launch_bwd<T, 16, 128, MODE_ONE, 256>(LB, Mx, bp, nsys, nrhs, W, st);
         if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
         return launch_bwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st);
