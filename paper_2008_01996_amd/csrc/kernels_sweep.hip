@@ -497,7 +497,7 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
             T* YIs = YI + (s & 1) * CB * NRS;
             const int c0 = s * CB;
             const int nb = min(CB, Mx - c0);
-            const cplx<T> dinv = cinv(L[k2 * ls]);
+            const cplx<T> dinv = cinv_fast(L[k2 * ls]);
             const int qs = wrap(cs + k2) * NRS;
             auto put_y = [&](int t, T vr, T vi) {
                 YRs[k2 * NRS + t] = vr;
@@ -551,12 +551,21 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
                 }
             }
             if (!LOADER_ENTER || bp < CB) {
-                // the rows entering the window take the slots of the block's rows
+                // the rows entering the window take the slots of the block's
+                // rows (with one right-hand side only its slot t = 0)
                 wave_lds_sync();
-                for (int q = lane; q < CB * NRS; q += 64) {
-                    const int sl = wrap(cs + q / NRS) * NRS + q % NRS;
-                    QR[sl] = SGR[q];
-                    QI[sl] = SGI[q];
+                if constexpr (ONE) {
+                    if (lane < CB) {
+                        const int sl = wrap(cs + lane) * NRS;
+                        QR[sl] = SGR[lane * NRS];
+                        QI[sl] = SGI[lane * NRS];
+                    }
+                } else {
+                    for (int q = lane; q < CB * NRS; q += 64) {
+                        const int sl = wrap(cs + q / NRS) * NRS + q % NRS;
+                        QR[sl] = SGR[q];
+                        QI[sl] = SGI[q];
+                    }
                 }
             }
         }
