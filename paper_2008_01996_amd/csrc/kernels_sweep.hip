@@ -4,20 +4,21 @@
 //     backward  L_k^T z_k = w
 //
 // Along one system the sweeps are a sequential chain of column blocks of CB
-// columns, and every factor entry is read once.  One workgroup of four waves
-// runs one system for up to NRS right-hand sides:
+// columns, and every factor entry is read once.  One workgroup (4 or 8
+// waves) runs one system for up to NRS right-hand sides:
 //   * wave 0 runs the critical path of each block alone, with no barrier
 //     inside the block: the CB x CB unit-triangular solve (one lane per row
 //     and right-hand side, values passed on by lane broadcasts, the lane's
 //     row of L held in registers) and the coupling to the adjacent block
 //     (forward: the update of the next block's rows; backward: the sums over
 //     the rows of the block just finished);
-//   * waves 1-3 stream the L entries of block i + 2 (with the right-hand-side
-//     values that block needs) into one of three LDS slots, their global
-//     loads issued two blocks ahead, and do the rest of the band coupling one
-//     block off the critical path (forward: the update of rows two or more
-//     blocks below by the block finished one step earlier; backward: the sums
-//     over rows two or more blocks below for the block processed next).
+//   * the other (loader) waves stream the L entries of block i + 2 (with
+//     the right-hand-side values that block needs) into one of three LDS
+//     slots, their global loads issued two blocks ahead, and do the rest of
+//     the band coupling one block off the critical path (forward: the update
+//     of rows two or more blocks below by the block finished one step
+//     earlier; backward: the sums over rows two or more blocks below for the
+//     block processed next).
 // One workgroup barrier per block hands slots and buffers over.  The pending
 // values of the bp + CB rows a block can touch (forward), or the finished z
 // of the rows below it (backward), live in an LDS ring.
@@ -136,7 +137,7 @@ __device__ __forceinline__ void deposit(const cplx<T> (&l)[EL], const cplx<T> (&
     }
 }
 
-// Forward, off the critical path (waves 1-3): rows c0 + CB + rr, rr in
+// Forward, off the critical path (loader waves): rows c0 + CB + rr, rr in
 // [CB, bp), of the pending ring take the update by block (c0, nb) with its
 // solution y.  cs = (c0 + CB) mod ring.  With PW > 1 the CB columns of a row
 // are split over PW lanes 64 / PW apart in a wave.
@@ -227,7 +228,7 @@ __device__ __forceinline__ void forward_far_update_multi(const cplx<T>* L, const
     }
 }
 
-// Backward, off the critical path (waves 1-3): for the full block at c0 and
+// Backward, off the critical path (loader waves): for the full block at c0 and
 // every column k, partial sums over rows r = c0 + 2 CB + m (m < bp - CB) of
 // L[r, c0 + k] z[r][t].  Lane li takes column k = li % CB and the RPC rows of
 // chunk li / CB; the chunks of a wave are added by shuffles and loader wave w
