@@ -56,6 +56,13 @@ extern "C" {
 
 #define STFD_MAX_HIST 64
 
+/* solution method (stfd_opts.method) */
+#define STFD_METHOD_FD 0   /* Fast Diagonalization, Algorithm FD (Sec. 4.4) */
+#define STFD_METHOD_BSC 1  /* Bartels-Stewart with the complex Schur form,
+                              Algorithm BSc (Sec. 4.3): unitary transforms, the
+                              N_t spatial systems solved one after the other;
+                              FP64 only */
+
 typedef struct stfd_space stfd_space;
 typedef struct stfd_problem stfd_problem;
 typedef struct stfd_batch stfd_batch;
@@ -71,6 +78,7 @@ typedef struct {
                              their FP32 rounding is amplified by kappa_2(X_t)). */
     double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
     int max_refine;       /* maximum number of refinement corrections (default 30) */
+    int method;           /* STFD_METHOD_FD (default) or STFD_METHOD_BSC */
 } stfd_opts;
 
 typedef struct {
@@ -181,10 +189,27 @@ int stfd_time_decompose(int Nt, const double* At, const double* Mt, double* lam_
                         stfd_setup_report* rep);
 
 /* ---------------------------------------------------------------------------
+ * Step 1 of Algorithm BSc (Sec. 4.3) on the host, for tests: the complex
+ * Schur form A_t^-1 M_t = W S W^* with W unitary and S upper triangular, the
+ * generalised eigenvalues of (Mt, At) on its diagonal (A_t^-1 M_t formed
+ * with the Cholesky factor of At, then Householder-Hessenberg reduction and
+ * shifted complex QR).  Outputs (caller-owned, Nt*Nt complex each, row-major,
+ * re/im interleaved: S[2*(i*Nt + j)] = Re S_ij): S, W.
+ * Errors: STFD_EINVAL, STFD_ENUMERIC (At not SPD, QR did not converge).
+ * Host only.
+ * ------------------------------------------------------------------------- */
+int stfd_time_schur(int Nt, const double* At, const double* Mt, double* S, double* W);
+
+/* ---------------------------------------------------------------------------
  * stfd_fd_setup: steps 1a/1b for the pencil (Mt, At) on the host in FP64,
  * plus the transform factors of steps 2 and 4, uploaded to the current HIP
  * device on hip_stream.  Copies At and Mt; space must outlive the problem.
- * opts may be NULL (defaults).
+ * opts may be NULL (defaults).  With opts->method = STFD_METHOD_BSC the
+ * problem follows Algorithm BSc instead: step 1 is the complex Schur form
+ * (as stfd_time_schur), the systems are all N_t diagonal entries of S (no
+ * pairing), step 2 is G = F^ A_t^-1 conj(W), step 4 U = Re(Z W^T); the
+ * factor, solve and apply entry points below then run that algorithm (FP64
+ * precision required, else STFD_EINVAL).
  * Errors: STFD_EINVAL, STFD_ENUMERIC, STFD_ENOMEM, STFD_EHIP.
  * ------------------------------------------------------------------------- */
 int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, const double* Mt,

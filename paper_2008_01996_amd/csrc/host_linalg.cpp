@@ -209,6 +209,21 @@ static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::st
     return true;
 }
 
+bool schur_real(int n, std::vector<double>& a, std::vector<cd>& t, std::vector<cd>& z, std::string* err) {
+    std::vector<double> q;
+    hessenberg(n, a, q);
+    t.assign((size_t)n * n, 0.0);
+    z.assign((size_t)n * n, 0.0);
+    for (size_t i = 0; i < t.size(); ++i) {
+        t[i] = a[i];
+        z[i] = q[i];
+    }
+    if (!schur_complex(n, t, z, err)) return false;
+    for (int i = 1; i < n; ++i)                          // exact zeros below the diagonal
+        for (int j = 0; j < i; ++j) t[(size_t)i * n + j] = 0.0;
+    return true;
+}
+
 bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<cd>& vecs,
               std::string* err) {
     std::vector<double> q;

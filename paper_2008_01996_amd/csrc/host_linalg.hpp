@@ -31,6 +31,12 @@ void chol_backward(int n, const std::vector<double>& L, cd* b, int nrhs);
 bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<cd>& vecs,
               std::string* err);
 
+// Complex Schur form of a real nonsymmetric matrix a (n x n, row-major,
+// destroyed): a = Z T Z^H with Z unitary and T upper triangular (row-major,
+// the eigenvalues on its diagonal).  Returns false if the QR iteration does
+// not converge.
+bool schur_real(int n, std::vector<double>& a, std::vector<cd>& t, std::vector<cd>& z, std::string* err);
+
 // One-sided Jacobi SVD of a complex n x n matrix: a = U diag(s) V^H.
 // a is row-major and destroyed; U, V row-major; s descending.
 bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,

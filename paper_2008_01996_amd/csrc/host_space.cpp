@@ -31,6 +31,7 @@ extern "C" int stfd_opts_default(stfd_opts* o) {
     o->fp64_transforms = 5;
     o->rtol = 1e-10;
     o->max_refine = 30;
+    o->method = STFD_METHOD_FD;
     return STFD_OK;
 }
 

@@ -52,11 +52,18 @@ hipError_t launch_band_init(void* LB, int Mx, int bp, int nsys, const int* rowpt
                             const double* valM, const double* valA, const double* lam, hipStream_t st);
 template <typename T>
 hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStream_t st);
+// sweeps of systems sys0 .. sys0 + nrun - 1 of the nsys (G, W laid out for all nsys)
 template <typename T>
 hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                               hipStream_t st);
+                               hipStream_t st, int sys0, int nrun);
 template <typename T>
-hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st);
+hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st,
+                                int sys0, int nrun);
+// Bartels-Stewart coupling after system k is solved (G [rhs][2 nsys][Mx], z_k
+// in columns k and nsys + k): v = A_x z_k, then g_i -= S[i][k] v for i < k
+// (S row-major nsys x nsys, complex interleaved)
+hipError_t launch_bs_update(int Mx, int nsys, int nrhs, int k, const int* rowptr, const int* col,
+                            const double* valA, const double* S, double* G, hipStream_t st);
 template <typename T>
 size_t band_ldl_smem(int bp);
 template <typename T>

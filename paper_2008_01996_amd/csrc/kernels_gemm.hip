@@ -204,6 +204,42 @@ hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, con
     return hipGetLastError();
 }
 
+// Bartels-Stewart with the complex Schur form (Alg. BSc, Sec. 4.3), step 3:
+// once z_k is solved, the right-hand sides of the systems still to come take
+// its coupling, g_i -= S[i][k] A_x z_k for i < k.  A thread takes one row:
+// v = (A_x z_k)[row] (complex, from the CSR row), then the k updates of that
+// row (for a fixed i the lanes of a wave touch consecutive rows).  G per RHS:
+// column-major Mx x 2 nsys, real parts in column i, imaginary in nsys + i.
+__global__ void __launch_bounds__(256) bs_update_kernel(int Mx, int nsys, int k, const int* __restrict__ rowptr,
+                                                        const int* __restrict__ col,
+                                                        const double* __restrict__ valA,
+                                                        const double* __restrict__ S, double* __restrict__ G) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Mx) return;
+    double* Gb = G + (size_t)blockIdx.y * 2 * nsys * Mx;
+    const double* zr = Gb + (size_t)k * Mx;
+    const double* zi = Gb + (size_t)(nsys + k) * Mx;
+    double vr = 0.0, vi = 0.0;
+    for (int e = rowptr[m]; e < rowptr[m + 1]; ++e) {
+        const double a = valA[e];
+        vr += a * zr[col[e]];
+        vi += a * zi[col[e]];
+    }
+    for (int i = 0; i < k; ++i) {
+        const double sr = S[2 * ((size_t)i * nsys + k)], si = S[2 * ((size_t)i * nsys + k) + 1];
+        Gb[(size_t)i * Mx + m] -= sr * vr - si * vi;
+        Gb[(size_t)(nsys + i) * Mx + m] -= sr * vi + si * vr;
+    }
+}
+
+hipError_t launch_bs_update(int Mx, int nsys, int nrhs, int k, const int* rowptr, const int* col,
+                            const double* valA, const double* S, double* G, hipStream_t st) {
+    if (k <= 0) return hipSuccess;
+    dim3 grid((Mx + 255) / 256, nrhs);
+    hipLaunchKernelGGL(bs_update_kernel, grid, dim3(256), 0, st, Mx, nsys, k, rowptr, col, valA, S, G);
+    return hipGetLastError();
+}
+
 // fixed-order reduction of the residual GEMM partial sums: norms[2 r] =
 // ||R_r||^2, norms[2 r + 1] = ||F_r||^2
 __global__ void reduce_partials_kernel(const double* __restrict__ partial, size_t blocks, double* __restrict__ norms) {

@@ -352,7 +352,7 @@ __device__ __forceinline__ void chain2(T& vr, T& vi, T& ar, T& ai, const cplx<T>
 template <typename T, int CB, int BPC, int MODE, int NTH>
 __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp_in,
                                                            int nsys, int nrhs, const T* __restrict__ G,
-                                                           T* __restrict__ W) {
+                                                           T* __restrict__ W, int sys0) {
     using C = Cfg<T, CB, BPC, NTH>;
     constexpr bool ONE = MODE == MODE_ONE || MODE == MODE_ONE_EXACT;
     const int bp = MODE == MODE_ONE_EXACT ? BPC : bp_in;
@@ -372,7 +372,7 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
     T* YI = YR + 2 * CB * NRS;
     T* PR = YI + 2 * CB * NRS;                    // update of the next block's rows, [CB][NRS]
     T* PI = PR + CB * NRS;
-    const int sys = blockIdx.x;
+    const int sys = sys0 + blockIdx.x;             // systems sys0 .. sys0 + gridDim.x - 1
     const int r0 = blockIdx.y * NRS;
     const int nr = min(NRS, nrhs - r0);
     const cplx<T>* base = LB + (size_t)sys * Mx * bp1;
@@ -578,7 +578,7 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
 // ---------------------------------------------------------------------------
 template <typename T, int CB, int BPC, int MODE, int NTH>
 __global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp_in,
-                                                            int nsys, int nrhs, T* __restrict__ W) {
+                                                            int nsys, int nrhs, T* __restrict__ W, int sys0) {
     using C = Cfg<T, CB, BPC, NTH>;
     constexpr bool ONE = MODE == MODE_ONE || MODE == MODE_ONE_EXACT;
     const int bp = MODE == MODE_ONE_EXACT ? BPC : bp_in;
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __re
     T* SI = SR + 2 * NP * CB * NRS;
     T* BR = SI + 2 * NP * CB * NRS;               // sums over the block just finished, [CB][NRS]
     T* BI = BR + CB * NRS;
-    const int sys = blockIdx.x;
+    const int sys = sys0 + blockIdx.x;             // systems sys0 .. sys0 + gridDim.x - 1
     const int r0 = blockIdx.y * NRS;
     const int nr = min(NRS, nrhs - r0);
     const cplx<T>* base = LB + (size_t)sys * Mx * bp1;
@@ -766,27 +766,28 @@ __global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __re
 // ---------------------------------------------------------------------------
 template <typename T, int CB, int BPC, int MODE, int NTH>
 static hipError_t launch_fwd(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                             hipStream_t st) {
+                             hipStream_t st, int sys0, int nrun) {
     const size_t smem = smem_elems<T, CB, BPC, NTH>(bp) * sizeof(T);
     hipError_t e = hipFuncSetAttribute((const void*)sweep_forward_kernel<T, CB, BPC, MODE, NTH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
+    dim3 grid(nrun, (nrhs + NRS - 1) / NRS);
     hipLaunchKernelGGL((sweep_forward_kernel<T, CB, BPC, MODE, NTH>), grid, dim3(NTH), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<const T*>(G),
-                       static_cast<T*>(W));
+                       static_cast<T*>(W), sys0);
     return hipGetLastError();
 }
 
 template <typename T, int CB, int BPC, int MODE, int NTH>
-static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
+static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st, int sys0,
+                             int nrun) {
     const size_t smem = smem_elems<T, CB, BPC, NTH>(bp) * sizeof(T);
     hipError_t e = hipFuncSetAttribute((const void*)sweep_backward_kernel<T, CB, BPC, MODE, NTH>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
-    dim3 grid(nsys, (nrhs + NRS - 1) / NRS);
+    dim3 grid(nrun, (nrhs + NRS - 1) / NRS);
     hipLaunchKernelGGL((sweep_backward_kernel<T, CB, BPC, MODE, NTH>), grid, dim3(NTH), smem, st,
-                       static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W));
+                       static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W), sys0);
     return hipGetLastError();
 }
 
@@ -808,15 +809,16 @@ constexpr int BWD_MULTI_MIN = 6;
 // general or multi-right-hand-side variant by the right-hand-side count
 template <typename T, int CB, int BPC, int NTH>
 static hipError_t launch_fwd_rhs(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                                 hipStream_t st) {
-    return nrhs >= FWD_MULTI_MIN ? launch_fwd<T, CB, BPC, MODE_MULTI, NTH>(LB, Mx, bp, nsys, nrhs, G, W, st)
-                                 : launch_fwd<T, CB, BPC, MODE_ANY, NTH>(LB, Mx, bp, nsys, nrhs, G, W, st);
+                                 hipStream_t st, int sys0, int nrun) {
+    return nrhs >= FWD_MULTI_MIN ? launch_fwd<T, CB, BPC, MODE_MULTI, NTH>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun)
+                                 : launch_fwd<T, CB, BPC, MODE_ANY, NTH>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
 }
 
 template <typename T, int CB, int BPC, int NTH>
-static hipError_t launch_bwd_rhs(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
-    return nrhs >= BWD_MULTI_MIN ? launch_bwd<T, CB, BPC, MODE_MULTI, NTH>(LB, Mx, bp, nsys, nrhs, W, st)
-                                 : launch_bwd<T, CB, BPC, MODE_ANY, NTH>(LB, Mx, bp, nsys, nrhs, W, st);
+static hipError_t launch_bwd_rhs(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st,
+                                 int sys0, int nrun) {
+    return nrhs >= BWD_MULTI_MIN ? launch_bwd<T, CB, BPC, MODE_MULTI, NTH>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun)
+                                 : launch_bwd<T, CB, BPC, MODE_ANY, NTH>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
 }
 
 template <typename T>
@@ -832,49 +834,52 @@ size_t sweep_smem(int bp) {
 
 template <typename T>
 hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
-                               hipStream_t st) {
-    if (bp > BPMAX) return hipErrorInvalidValue;
+                               hipStream_t st, int sys0, int nrun) {
+    if (bp > BPMAX || sys0 < 0 || nrun < 1 || sys0 + nrun > nsys) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
         if (bp == 128 && nrhs == 1)
-            return launch_fwd<T, 32, 128, MODE_ONE_EXACT, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        if (bp <= 128 && nrhs == 1) return launch_fwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
+            return launch_fwd<T, 32, 128, MODE_ONE_EXACT, 512>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+        if (bp <= 128 && nrhs == 1) return launch_fwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
         if (bp <= 128 && nrhs < FWD_MULTI_MIN)
-            return launch_fwd<T, 32, 128, MODE_ANY, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        if (bp <= 128) return launch_fwd<T, 16, 128, MODE_MULTI, 512>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        return launch_fwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+            return launch_fwd<T, 32, 128, MODE_ANY, 256>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+        if (bp <= 128) return launch_fwd<T, 16, 128, MODE_MULTI, 512>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+        return launch_fwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
     } else {
         if (bp == 128 && nrhs == 1)
-            return launch_fwd<T, 16, 128, MODE_ONE_EXACT, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        if (bp <= 128 && nrhs == 1) return launch_fwd<T, 16, 128, MODE_ONE, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        if (bp <= 128) return launch_fwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
-        return launch_fwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st);
+            return launch_fwd<T, 16, 128, MODE_ONE_EXACT, 256>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+        if (bp <= 128 && nrhs == 1) return launch_fwd<T, 16, 128, MODE_ONE, 256>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+        if (bp <= 128) return launch_fwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+        return launch_fwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
     }
 }
 
 template <typename T>
-hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st) {
-    if (bp > BPMAX) return hipErrorInvalidValue;
+hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nrhs, void* W, hipStream_t st,
+                                int sys0, int nrun) {
+    if (bp > BPMAX || sys0 < 0 || nrun < 1 || sys0 + nrun > nsys) return hipErrorInvalidValue;
     if constexpr (sizeof(T) == 4) {
         if (bp == 128 && nrhs == 1)
-            return launch_bwd<T, 32, 128, MODE_ONE_EXACT, 512>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128 && nrhs == 1) return launch_bwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128 && nrhs < MULTI_RHS) return launch_bwd_rhs<T, 32, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
-        return launch_bwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+            return launch_bwd<T, 32, 128, MODE_ONE_EXACT, 512>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        if (bp <= 128 && nrhs == 1) return launch_bwd<T, 32, 128, MODE_ONE, 512>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        if (bp <= 128 && nrhs < MULTI_RHS) return launch_bwd_rhs<T, 32, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        return launch_bwd_rhs<T, 16, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
     } else {
-        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_rhs<T, 8, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+        if (bp <= 128 && nrhs >= MULTI_RHS) return launch_bwd_rhs<T, 8, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
         if (bp == 128 && nrhs == 1)
-            return launch_bwd<T, 16, 128, MODE_ONE_EXACT, 256>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128 && nrhs == 1) return launch_bwd<T, 16, 128, MODE_ONE, 256>(LB, Mx, bp, nsys, nrhs, W, st);
-        if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st);
-        return launch_bwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st);
+            return launch_bwd<T, 16, 128, MODE_ONE_EXACT, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        if (bp <= 128 && nrhs == 1) return launch_bwd<T, 16, 128, MODE_ONE, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        if (bp <= 128) return launch_bwd_rhs<T, 16, 128, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
+        return launch_bwd_rhs<T, 8, 256, 256>(LB, Mx, bp, nsys, nrhs, W, st, sys0, nrun);
     }
 }
 
-template hipError_t launch_band_forward<float>(const void*, int, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_band_forward<double>(const void*, int, int, int, int, const void*, void*, hipStream_t);
-template hipError_t launch_band_backward<float>(const void*, int, int, int, int, void*, hipStream_t);
-template hipError_t launch_band_backward<double>(const void*, int, int, int, int, void*, hipStream_t);
+template hipError_t launch_band_forward<float>(const void*, int, int, int, int, const void*, void*, hipStream_t, int,
+                                               int);
+template hipError_t launch_band_forward<double>(const void*, int, int, int, int, const void*, void*, hipStream_t, int,
+                                                int);
+template hipError_t launch_band_backward<float>(const void*, int, int, int, int, void*, hipStream_t, int, int);
+template hipError_t launch_band_backward<double>(const void*, int, int, int, int, void*, hipStream_t, int, int);
 template size_t sweep_smem<float>(int);
 template size_t sweep_smem<double>(int);
 

@@ -22,6 +22,7 @@ struct stfd_problem {
     const stfd_space* space = nullptr;
     stfd_opts opts{};
     int Nt = 0, Mx = 0, b = 0, bp = 0, nsys = 0, npair = 0, nreal = 0;
+    int method = STFD_METHOD_FD;
     stfd_setup_report rep{};
     std::vector<double> lam_sys;   // 2 nsys (re, im)
     bool factored = false;
@@ -38,6 +39,7 @@ struct stfd_problem {
     double* d_W2d = nullptr;    // FP64 copies for FP64 transforms in the FP32 form
     double* d_Xbd = nullptr;
     double* d_Bres = nullptr;   // 2Nt x Nt     [A_t^T; M_t^T]
+    double* d_S = nullptr;      // Alg. BSc: Nt x Nt upper-triangular Schur factor, complex interleaved
     void* d_LB = nullptr;       // band factors
     int* d_flag = nullptr;
     // work buffers, sized for nrhs_cap right-hand sides
@@ -342,6 +344,155 @@ extern "C" int stfd_time_decompose(int Nt, const double* At, const double* Mt, d
     return STFD_OK;
 }
 
+namespace {
+
+// Step 1 of Algorithm BSc: A_t^-1 M_t = W S W^* (S upper triangular, W unitary)
+int time_schur(int n, const double* At, const double* Mt, std::vector<cd>& S, std::vector<cd>& W) {
+    for (size_t i = 0; i < (size_t)n * n; ++i)
+        if (!std::isfinite(At[i]) || !std::isfinite(Mt[i])) return fail(STFD_ENUMERIC, "non-finite time matrix");
+    std::vector<double> L(At, At + (size_t)n * n);
+    if (!stfd::cholesky(n, L)) return fail(STFD_ENUMERIC, "A_t is not symmetric positive definite");
+    std::vector<double> C(Mt, Mt + (size_t)n * n);     // column r of C solves A_t c = M_t[:, r]
+    stfd::chol_forward(n, L, C.data(), n);
+    stfd::chol_backward(n, L, C.data(), n);
+    std::string err;
+    if (!stfd::schur_real(n, C, S, W, &err)) return fail(STFD_ENUMERIC, "Schur form: " + err);
+    return STFD_OK;
+}
+
+// stfd_fd_setup for Algorithm BSc (FP64): Schur form, transforms, uploads
+int bs_setup(const stfd_space* space, int n, const double* At, const double* Mt, const stfd_opts& o,
+             hipStream_t st, stfd_problem** out) {
+    if (o.precision != STFD_PREC_FP64) return fail(STFD_EINVAL, "fd_setup: the Bartels-Stewart method runs in FP64");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<cd> S, W;
+    int rc = time_schur(n, At, Mt, S, W);
+    if (rc) return rc;
+    auto* p = new (std::nothrow) stfd_problem();
+    if (!p) return fail(STFD_ENOMEM, "fd_setup: out of memory");
+    p->space = space;
+    p->opts = o;
+    p->method = STFD_METHOD_BSC;
+    p->Nt = n;
+    p->Mx = space->Mx;
+    p->b = space->half_band;
+    p->bp = std::max(16, (p->b + 15) / 16 * 16);
+    p->nsys = n;
+    if (std::max(stfd::band_ldl_smem<double>(p->bp), stfd::sweep_smem<double>(p->bp)) > 160 * 1024) {
+        delete p;
+        return fail(STFD_EINVAL, "fd_setup: half-bandwidth too large for the LDS-staged kernels in FP64");
+    }
+    // systems: the diagonal of S; report
+    p->lam_sys.resize(2 * n);
+    double min_re = HUGE_VAL, max_abs = 0.0;
+    int nreal = 0;
+    for (int k = 0; k < n; ++k) {
+        const cd l = S[(size_t)k * n + k];
+        p->lam_sys[2 * k] = l.real();
+        p->lam_sys[2 * k + 1] = l.imag();
+        min_re = std::min(min_re, l.real());
+        max_abs = std::max(max_abs, std::abs(l));
+        if (std::fabs(l.imag()) <= 1e-12 * std::abs(l)) ++nreal;
+    }
+    if (!(min_re > 0.0)) {
+        delete p;
+        return fail(STFD_ENUMERIC, "fd_setup: an eigenvalue has Re(lambda) <= 0");
+    }
+    p->nreal = nreal;
+    p->npair = (n - nreal) / 2;
+    p->rep.min_re_lambda = min_re;
+    p->rep.max_abs_lambda = max_abs;
+    p->rep.sigma_min = p->rep.sigma_max = p->rep.kappa2 = 1.0;   // W unitary
+    p->rep.n_real = nreal;
+    p->rep.n_pairs = p->npair;
+    p->rep.n_sys = n;
+    p->rep.half_band = p->b;
+    {
+        // ||A_t^-1 M_t W - W S||_F / ||A_t^-1 M_t||_F, with A_t^-1 M_t rebuilt as W S W^*
+        std::vector<double> L(At, At + (size_t)n * n);
+        stfd::cholesky(n, L);
+        std::vector<double> C(Mt, Mt + (size_t)n * n);
+        stfd::chol_forward(n, L, C.data(), n);
+        stfd::chol_backward(n, L, C.data(), n);
+        double num = 0.0, den = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                cd cw = 0.0, ws = 0.0;
+                for (int m = 0; m < n; ++m) cw += C[(size_t)i * n + m] * W[(size_t)m * n + j];
+                for (int m = 0; m <= j; ++m) ws += W[(size_t)i * n + m] * S[(size_t)m * n + j];
+                num += std::norm(cw - ws);
+                den += C[(size_t)i * n + j] * C[(size_t)i * n + j];
+            }
+        p->rep.eig_residual = std::sqrt(num / std::max(den, 1e-300));
+    }
+    // step 2 factor W1 = A_t^-1 conj(W) -> [Re | Im] (n x 2n); step 4 factor
+    // Xb = [Re W^T; -Im W^T] (2n x n): Re(Z W^T) = Zr Wr^T - Zi Wi^T
+    std::vector<double> L(At, At + (size_t)n * n);
+    stfd::cholesky(n, L);
+    std::vector<cd> W1((size_t)n * n);
+    for (size_t i = 0; i < W1.size(); ++i) W1[i] = std::conj(W[i]);
+    stfd::chol_forward(n, L, W1.data(), n);
+    stfd::chol_backward(n, L, W1.data(), n);
+    std::vector<double> W1h((size_t)n * 2 * n), Xbh((size_t)2 * n * n), Sh((size_t)2 * n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            W1h[(size_t)i * 2 * n + j] = W1[(size_t)i * n + j].real();
+            W1h[(size_t)i * 2 * n + n + j] = W1[(size_t)i * n + j].imag();
+            Xbh[(size_t)j * n + i] = W[(size_t)i * n + j].real();
+            Xbh[(size_t)(n + j) * n + i] = -W[(size_t)i * n + j].imag();
+            Sh[2 * ((size_t)i * n + j)] = S[(size_t)i * n + j].real();
+            Sh[2 * ((size_t)i * n + j) + 1] = S[(size_t)i * n + j].imag();
+        }
+    std::vector<double> Bres((size_t)2 * n * n);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) {
+            Bres[(size_t)j * n + k] = At[(size_t)k * n + j];
+            Bres[(size_t)(n + j) * n + k] = Mt[(size_t)k * n + j];
+        }
+    const stfd_space* s = space;
+    int zero = 0, e = 0;
+    if ((e = upload(&p->d_rowptr, s->rowptr.data(), s->rowptr.size() * sizeof(int), st)) ||
+        (e = upload(&p->d_col, s->col.data(), s->col.size() * sizeof(int), st)) ||
+        (e = upload(&p->d_valM, s->valM.data(), s->valM.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_valA, s->valA.data(), s->valA.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_lam, p->lam_sys.data(), p->lam_sys.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_W1, W1h.data(), W1h.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_Xb, Xbh.data(), Xbh.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_S, Sh.data(), Sh.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_Bres, Bres.data(), Bres.size() * sizeof(double), st)) ||
+        (e = upload(&p->d_flag, &zero, sizeof(int), st))) {
+        stfd_problem_free(p);
+        return e;
+    }
+    hipError_t he = hipStreamSynchronize(st);            // host sources go out of scope
+    if (he != hipSuccess) {
+        stfd_problem_free(p);
+        return hip_fail(he, "fd_setup: stream synchronize");
+    }
+    p->rep.factor_bytes = (double)n * p->Mx * (p->bp + 1) * 16;
+    p->rep.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+}  // namespace
+
+extern "C" int stfd_time_schur(int Nt, const double* At, const double* Mt, double* S, double* W) {
+    if (Nt < 1 || !At || !Mt || !S || !W) return fail(STFD_EINVAL, "time_schur: bad arguments");
+    std::vector<cd> Sv, Wv;
+    int rc = time_schur(Nt, At, Mt, Sv, Wv);
+    if (rc) return rc;
+    for (size_t i = 0; i < (size_t)Nt * Nt; ++i) {
+        S[2 * i] = Sv[i].real();
+        S[2 * i + 1] = Sv[i].imag();
+        W[2 * i] = Wv[i].real();
+        W[2 * i + 1] = Wv[i].imag();
+    }
+    stfd::clear_error();
+    return STFD_OK;
+}
+
 extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, const double* Mt,
                              const stfd_opts* opts, void* hip_stream, stfd_problem** out) {
     if (!space || Nt < 1 || !At || !Mt || !out) return fail(STFD_EINVAL, "fd_setup: bad arguments");
@@ -350,8 +501,10 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     stfd_opts_default(&o);
     if (opts) o = *opts;
     if ((o.precision != STFD_PREC_FP32 && o.precision != STFD_PREC_FP64) || !(o.rtol >= 0.0) || o.max_refine < 0 ||
-        o.max_refine >= STFD_MAX_HIST || o.fp64_transforms < 0 || o.fp64_transforms > 7)
+        o.max_refine >= STFD_MAX_HIST || o.fp64_transforms < 0 || o.fp64_transforms > 7 ||
+        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC))
         return fail(STFD_EINVAL, "fd_setup: bad options");
+    if (o.method == STFD_METHOD_BSC) return bs_setup(space, Nt, At, Mt, o, static_cast<hipStream_t>(hip_stream), out);
     const auto t0 = std::chrono::steady_clock::now();
     Decomp D;
     int rc = decompose_cached(Nt, At, Mt, D);
@@ -529,14 +682,14 @@ int spatial_sweeps(stfd_problem* p, int nrhs, const void* G, void* Z, hipStream_
     const bool f32 = is_fp32(p);
     {
         StageTimer tm(p, STFD_ST_SWEEP_FWD, st);
-        HIPCHK(f32 ? stfd::launch_band_forward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st)
-                   : stfd::launch_band_forward<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st),
+        HIPCHK(f32 ? stfd::launch_band_forward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0, p->nsys)
+                   : stfd::launch_band_forward<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0, p->nsys),
                "forward sweep");
     }
     {
         StageTimer tm(p, STFD_ST_SWEEP_BWD, st);
-        HIPCHK(f32 ? stfd::launch_band_backward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, Z, st)
-                   : stfd::launch_band_backward<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, Z, st),
+        HIPCHK(f32 ? stfd::launch_band_backward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, Z, st, 0, p->nsys)
+                   : stfd::launch_band_backward<double>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, Z, st, 0, p->nsys),
                "backward sweep");
     }
     return STFD_OK;
@@ -595,6 +748,59 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     return STFD_OK;
 }
 
+// one application of Algorithm BSc: X -> U += BSc(X)
+int bs_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t st) {
+    const int Mx = p->Mx, n = p->Nt;
+    // step 2: G = X A_t^-1 conj(W)  (Mx x 2n: real parts, then imaginary parts)
+    stfd::GemmArgs g{};
+    g.A = X; g.B = p->d_W1; g.C = p->d_G;
+    g.M = Mx; g.N = 2 * n; g.K = n;
+    g.lda = Mx; g.ldb = 2 * n; g.ldc = Mx;
+    g.strideA = (long long)Mx * n; g.strideC = (long long)Mx * 2 * n;
+    g.batch = nrhs;
+    {
+        StageTimer tm(p, STFD_ST_FWD1, st);
+        HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_STORE_D, g, st), "BSc forward transform");
+    }
+    // step 3: systems k = n-1 .. 0 one after the other; each solved z_k is
+    // coupled into the right-hand sides of the systems before it
+    for (int k = n - 1; k >= 0; --k) {
+        {
+            StageTimer tm(p, STFD_ST_SWEEP_FWD, st);
+            HIPCHK(stfd::launch_band_forward<double>(p->d_LB, Mx, p->bp, n, nrhs, p->d_G, p->d_G, st, k, 1),
+                   "BSc forward sweep");
+        }
+        {
+            StageTimer tm(p, STFD_ST_SWEEP_BWD, st);
+            HIPCHK(stfd::launch_band_backward<double>(p->d_LB, Mx, p->bp, n, nrhs, p->d_G, st, k, 1),
+                   "BSc backward sweep");
+        }
+        if (k > 0) {
+            StageTimer tm(p, STFD_ST_SPATIAL, st);
+            HIPCHK(stfd::launch_bs_update(Mx, n, nrhs, k, p->d_rowptr, p->d_col, p->d_valA, p->d_S,
+                                          static_cast<double*>(p->d_G), st),
+                   "BSc coupling");
+        }
+    }
+    // step 4: U += Re(Z W^T)
+    g = stfd::GemmArgs{};
+    g.A = p->d_G; g.B = p->d_Xb; g.C = U;
+    g.M = Mx; g.N = n; g.K = 2 * n;
+    g.lda = Mx; g.ldb = n; g.ldc = Mx;
+    g.strideA = (long long)Mx * 2 * n; g.strideC = (long long)Mx * n;
+    g.batch = nrhs; g.alpha = 1.0;
+    {
+        StageTimer tm(p, STFD_ST_BACK, st);
+        HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_ADD_D, g, st), "BSc back transform");
+    }
+    return STFD_OK;
+}
+
+// one application of the problem's method
+int method_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t st) {
+    return p->method == STFD_METHOD_BSC ? bs_apply(p, nrhs, X, U, st) : fd_apply(p, nrhs, X, U, st);
+}
+
 // R = F - K_h U and squared norms (device) for nrhs blocks
 int residual(stfd_problem* p, int nrhs, const double* F, const double* U, double* R, hipStream_t st) {
     const int Mx = p->Mx, Nt = p->Nt;
@@ -647,7 +853,7 @@ extern "C" int stfd_fd_apply(stfd_problem* p, int nrhs, const double* X_dev, dou
     int rc = ensure_work(p, nrhs);
     if (rc) return rc;
     HIPCHK(stfd::launch_fill_zero(U_dev, (size_t)p->Mx * p->Nt * nrhs, st), "zero U");
-    rc = fd_apply(p, nrhs, X_dev, U_dev, st);
+    rc = method_apply(p, nrhs, X_dev, U_dev, st);
     if (rc) return rc;
     stfd::clear_error();
     return STFD_OK;
@@ -686,7 +892,7 @@ extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, dou
     const double* X = F_dev;
     int status = STFD_ENOCONV;
     for (int it = 0; it <= p->opts.max_refine; ++it) {
-        rc = fd_apply(p, nrhs, X, U_dev, st);
+        rc = method_apply(p, nrhs, X, U_dev, st);
         if (rc) return rc;
         rc = residual(p, nrhs, F_dev, U_dev, p->d_R, st);
         if (rc) return rc;
@@ -790,7 +996,7 @@ extern "C" int stfd_batch_solve(stfd_batch* b, const int* nrhs, const double* co
         for (int i = 0; i < np; ++i) {
             if (!active[i]) continue;
             stfd_problem* p = b->probs[i];
-            int rc = fd_apply(p, nrhs[i], X[i], U_dev[i], st);
+            int rc = method_apply(p, nrhs[i], X[i], U_dev[i], st);
             if (rc) return rc;
             rc = residual(p, nrhs[i], F_dev[i], U_dev[i], p->d_R, st);
             if (rc) return rc;
@@ -892,6 +1098,7 @@ extern "C" void stfd_problem_free(stfd_problem* p) {
     (void)hipFree(p->d_W2d);
     (void)hipFree(p->d_Xbd);
     (void)hipFree(p->d_Bres);
+    (void)hipFree(p->d_S);
     (void)hipFree(p->d_LB);
     (void)hipFree(p->d_flag);
     delete p;

@@ -17,12 +17,13 @@ LIB_PATH = os.path.join(HERE, "libstfd.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, ENOCONV, ESTATE = 0, -1, -2, -3, -4, -5, -6
 PREC_FP64, PREC_FP32 = 0, 1
+METHOD_FD, METHOD_BSC = 0, 1
 MAX_HIST = 64
 
 EXPORTED = [
     "stfd_opts_default", "stfd_last_error", "stfd_assemble_time", "stfd_space_create",
     "stfd_space_free", "stfd_space_info", "stfd_space_csr_size", "stfd_space_export_csr",
-    "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_fd_setup",
+    "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_time_schur", "stfd_fd_setup",
     "stfd_fd_setup_report", "stfd_fd_factor", "stfd_fd_solve", "stfd_kh_residual",
     "stfd_problem_free", "stfd_fd_apply", "stfd_spatial_solve", "stfd_system_lambdas",
     "stfd_profile", "stfd_profile_read", "stfd_batch_create", "stfd_batch_factor", "stfd_batch_solve",
@@ -41,7 +42,7 @@ class StfdError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("fp64_transforms", C.c_int), ("rtol", C.c_double),
-                ("max_refine", C.c_int)]
+                ("max_refine", C.c_int), ("method", C.c_int)]
 
 
 class SetupReport(C.Structure):
@@ -94,6 +95,7 @@ def lib():
         L.stfd_project_f.argtypes = [vp, C.c_int, dp, C.c_int, C.c_int, ip, ip, ip, dp, dp, dp]
         L.stfd_assemble_load.argtypes = [vp, C.c_int, dp, dp, dp]
         L.stfd_time_decompose.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.POINTER(SetupReport)]
+        L.stfd_time_schur.argtypes = [C.c_int, dp, dp, dp, dp]
         L.stfd_fd_setup.argtypes = [vp, C.c_int, dp, dp, C.POINTER(Opts), vp, C.POINTER(vp)]
         L.stfd_fd_setup_report.argtypes = [vp, C.POINTER(SetupReport)]
         L.stfd_fd_factor.argtypes = [vp, vp]
@@ -156,6 +158,17 @@ def time_decompose(At, Mt):
     _check(lib().stfd_time_decompose(n, _dp(At), _dp(Mt), _dp(lr), _dp(li), _dp(Xr), _dp(Xi), _dp(s),
                                       C.byref(rep)))
     return lr + 1j * li, Xr + 1j * Xi, s, rep.as_dict()
+
+
+def time_schur(At, Mt):
+    """Host step 1 of Algorithm BSc: A_t^-1 M_t = W S W^* with W unitary and
+    S upper triangular.  Returns (S, W)."""
+    At = _f64(At)
+    Mt = _f64(Mt)
+    n = At.shape[0]
+    S, W = np.empty(2 * n * n), np.empty(2 * n * n)
+    _check(lib().stfd_time_schur(n, _dp(At), _dp(Mt), _dp(S), _dp(W)))
+    return (S[0::2] + 1j * S[1::2]).reshape(n, n), (W[0::2] + 1j * W[1::2]).reshape(n, n)
 
 
 class Space:
@@ -222,13 +235,14 @@ def _stream_ptr(stream):
 
 
 class Problem:
-    """FD solver for one (space, time mesh) pair on the current GPU."""
+    """Space-time solver (Algorithm FD, or BSc) for one (space, time mesh) pair on the current GPU."""
 
     def __init__(self, space: Space, At, Mt, precision="fp32", fp64_transforms=5, rtol=1e-10, max_refine=30,
-                 stream=None):
+                 stream=None, method="fd"):
         """fp64_transforms (FP32 form only): bit mask of the transform GEMMs run
         on FP64 matrix cores, bit 0 first forward, bit 1 second forward, bit 2
-        back transform."""
+        back transform.  method "fd" (Algorithm FD) or "bsc" (Algorithm BSc,
+        Bartels-Stewart with the complex Schur form; precision "fp64")."""
         self.space = space        # keep alive: the problem refers to it
         At = _f64(At)
         Mt = _f64(Mt)
@@ -240,7 +254,9 @@ class Problem:
         o.fp64_transforms = int(fp64_transforms)
         o.rtol = float(rtol)
         o.max_refine = int(max_refine)
+        o.method = {"fd": METHOD_FD, "bsc": METHOD_BSC}[method]
         self.precision = precision
+        self.method = method
         self._h = C.c_void_p()
         _check(lib().stfd_fd_setup(space._h, self.Nt, _dp(At), _dp(Mt), C.byref(o),
                                    C.c_void_p(_stream_ptr(stream)), C.byref(self._h)))

@@ -14,6 +14,7 @@ import math
 
 import numpy as np
 import pytest
+import scipy.linalg as sl
 
 import workloads as w
 from oracle import load
@@ -200,6 +201,63 @@ def test_single_application_matches_oracle_fd(precision, ncx, ncy, nrhs):
         worst = max(worst, np.linalg.norm(Uq - Uo) / np.linalg.norm(Uo))
     print(f"  one application: worst rel diff vs oracle FD {worst:.2e} (bound {tol:.2e})")
     assert worst <= tol
+
+
+# Algorithm BSc (Bartels-Stewart with the complex Schur form, Sec. 4.3): the
+# N_t systems solved one after the other through the same band kernels.
+BSC_CASES = [("square12", w.square_mesh(12), w.uniform_times(16), 1),
+             ("graded7", w.square_mesh(9), w.graded_times(7), 2),
+             ("band120", w.rect_mesh(120, 3), w.uniform_times(10), 3),
+             ("lshape16", w.lshape_mesh(16), w.paper_times(2), 1)]
+
+
+@pytest.mark.parametrize("name,mesh,t,nrhs", BSC_CASES, ids=[c[0] for c in BSC_CASES])
+def test_bartels_stewart_solve_matches_oracle(name, mesh, t, nrhs):
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[9000 + r for r in range(nrhs)])
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision="fp64", method="bsc", rtol=SOLVE_RTOL)
+    assert prob.setup_report["n_sys"] == len(t) - 1 and prob.setup_report["kappa2"] == 1.0
+    prob.factor()
+    F = _to_dev(Fs)
+    U = torch.empty_like(F)
+    rep = prob.solve(F, U)
+    torch.cuda.synchronize()
+    Us = [u.T.copy() for u in U.cpu().numpy()]
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
+@pytest.mark.parametrize("name,mesh,t,nrhs", BSC_CASES[:3], ids=[c[0] for c in BSC_CASES[:3]])
+def test_bartels_stewart_single_application_matches_oracle(name, mesh, t, nrhs):
+    """One application of Algorithm BSc against the oracle's.  W is unitary,
+    so the transforms add only ~N_t u; each spatial solve adds up to
+    (b + 1) u kappa_2(M_x + lambda_k A_x) (banded LU without pivoting), and
+    the substitution over S passes those on: both sides are within
+    N_t (b + 1) u max_k kappa_2(M_x + lambda_k A_x) of the exact solution."""
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[9100 + r for r in range(nrhs)])
+    sp_ = stfd.Space(mesh)
+    prob = stfd.Problem(sp_, At, Mt, precision="fp64", method="bsc")
+    prob.factor()
+    X = _to_dev(Fs)
+    U = torch.empty_like(X)
+    prob.apply(X, U)
+    torch.cuda.synchronize()
+    Us = [u.T.copy() for u in U.cpu().numpy()]
+    lam = sl.eigvals(Mt, At)
+    kmax = max(np.linalg.cond((Mx + l * Ax).toarray()) for l in lam)
+    tol = 2 * (len(t) - 1) * (sp_.half_band + 1) * np.finfo(float).eps * kmax
+    worst = 0.0
+    for Fq, Uq in zip(Fs, Us):
+        Uo = so.bartels_stewart(At, Mt, Mx, Ax, Fq)
+        worst = max(worst, np.linalg.norm(Uq - Uo) / np.linalg.norm(Uo))
+    print(f"  one BSc application: worst rel diff vs oracle {worst:.2e} (bound {tol:.2e})")
+    assert worst <= tol
+
+
+def test_bartels_stewart_requires_fp64():
+    mesh = w.square_mesh(4)
+    At, Mt, _, _, _ = _oracle_case(mesh, w.uniform_times(4), "random")
+    with pytest.raises(stfd.StfdError) as e:
+        stfd.Problem(stfd.Space(mesh), At, Mt, precision="fp32", method="bsc")
+    assert e.value.code == stfd.EINVAL
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

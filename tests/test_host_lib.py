@@ -122,6 +122,25 @@ def test_time_decompose_matches_oracle(t):
     assert rep["min_re_lambda"] > 0 and rep["eig_residual"] < 1e-13
 
 
+@pytest.mark.parametrize("t", [w.paper_times(0), w.uniform_times(16), w.graded_times(33)],
+                         ids=["paper0", "uniform16", "graded33"])
+def test_time_schur_is_a_schur_form(t):
+    """Step 1 of Algorithm BSc on the host: A_t^-1 M_t = W S W^* with W
+    unitary and S upper triangular, checked by its definition; its diagonal
+    is the multiset of generalised eigenvalues of (M_t, A_t)."""
+    A, M, _ = tm.kernel(t)
+    S, W = stfd.time_schur(A, M)
+    n = A.shape[0]
+    C = np.linalg.solve(A, M)
+    eps = np.finfo(float).eps
+    assert np.abs(W.conj().T @ W - np.eye(n)).max() <= 100 * n * eps
+    assert np.all(np.tril(S, -1) == 0)
+    assert np.linalg.norm(C @ W - W @ S) <= 100 * n * eps * np.linalg.norm(C)
+    lo = sl.eigvals(M, A)
+    kappa = so.decompose(A, M, normalization="unit").kappa
+    assert _match(np.diag(S), lo) <= 50 * eps * kappa * np.abs(lo).max()
+
+
 def test_error_paths():
     t = w.uniform_times(4)
     A, M, _ = tm.kernel(t)

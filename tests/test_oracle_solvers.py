@@ -51,6 +51,19 @@ def test_fd_matches_full_system(nc, t):
     assert hist[-1] < 1e-13
 
 
+@pytest.mark.parametrize("nc,t", [(16, w.uniform_times(16)), (8, w.paper_times(1)),
+                                  (6, w.graded_times(7))], ids=["C1", "paper1", "graded7"])
+def test_bartels_stewart_matches_full_system(nc, t):
+    """Algorithm BSc (unitary transforms, no refinement) equals the sparse LU
+    solution of the written-out K_h to 1e-12: with W unitary the transforms
+    amplify nothing, so plain BSc is accurate to rounding."""
+    _, At, Mt, Mx, Ax, F = _problem(nc, t)
+    Ud = so.direct(At, Mt, Mx, Ax, F)
+    Ub = so.bartels_stewart(At, Mt, Mx, Ax, F)
+    assert np.linalg.norm(Ub - Ud) / np.linalg.norm(Ud) < 1e-12
+    assert so.rel_residual(At, Mt, Mx, Ax, F, Ub) < 1e-13
+
+
 def test_single_time_element_is_one_spatial_solve():
     """N_t = 1: FD reduces to (A_t M_x + M_t A_x) u = F~ with lambda = M_t/A_t."""
     t = np.array([0.0, 0.6])
