@@ -232,7 +232,7 @@ def build_loads(mesh, t, modes):
     return sp, A, M, np.ascontiguousarray(np.stack(Fl))
 
 
-def run_gpu(loads, t, precision, steps, warmup):
+def run_gpu(loads, t, precision, steps, warmup, method="fd"):
     import torch
 
     from paper_2008_01996_amd import stfd
@@ -241,10 +241,10 @@ def run_gpu(loads, t, precision, steps, warmup):
     F = torch.from_numpy(Fh).to("cuda:0")
     U = torch.empty_like(F)
     torch.cuda.synchronize()
-    print(f"# {precision}: host setup (eigendecomposition, SVD) for N_t = {len(t) - 1} ...", file=sys.stderr,
-          flush=True)
+    what = "complex Schur form" if method == "bsc" else "eigendecomposition, SVD"
+    print(f"# {method} {precision}: host setup ({what}) for N_t = {len(t) - 1} ...", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    prob = stfd.Problem(sp, A, M, precision=precision, rtol=RTOL, max_refine=30)
+    prob = stfd.Problem(sp, A, M, precision=precision, rtol=RTOL, max_refine=30, method=method)
     setup_s = time.perf_counter() - t0
     print(f"# {precision}: setup {setup_s:.1f} s; warmup", file=sys.stderr, flush=True)
     for _ in range(warmup):
@@ -266,6 +266,55 @@ def run_gpu(loads, t, precision, steps, warmup):
     Uh = U.cpu().numpy()
     return {"sec": sec, "setup_s": setup_s, "reps": reps, "prof": prof, "U": Uh,
             "setup": prob.setup_report, "Mx": sp.Mx, "b": sp.half_band}
+
+
+def cpu_bsc(mesh, t, modes, budget_s):
+    """The oracle's Algorithm BSc on the host cores (one BLAS thread), RHS 0:
+    the whole algorithm when N_t spatial solves fit the budget, else steps
+    1, 2 and 4 in full and a sample of the sequential step 3 scaled to N_t."""
+    from threadpoolctl import threadpool_limits
+
+    import scipy.linalg as sl
+
+    from oracle import load
+    from oracle import solvers as so
+    from oracle import space_matrices as sm
+    from oracle import time_matrices as tm
+
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, M10 = sm.assemble(mesh)
+    md, kind = modes[0]
+    Fc = load.manufactured_cell_means(mesh, t) if kind == 1 else load.modes_cell_means(mesh, t, md)
+    F = load.assemble_load(M10, Fc, Ct)
+    nt = At.shape[0]
+    dofs = Mx.shape[0] * nt
+    with threadpool_limits(1):
+        g = np.ones(Mx.shape[0], dtype=complex)
+        t0 = time.perf_counter()
+        so._spatial_solve((Mx, Ax, 0.1 + 0.1j, g))
+        per_solve = time.perf_counter() - t0
+        if nt * per_solve <= budget_s:
+            t0 = time.perf_counter()
+            so.bartels_stewart(At, Mt, Mx, Ax, F)
+            sec = time.perf_counter() - t0
+            sample = f"full Algorithm BSc on RHS 0, {sec:.1f} s"
+        else:
+            t0 = time.perf_counter()
+            S, W = sl.schur(np.linalg.solve(At, Mt), output="complex")
+            G = F @ np.linalg.solve(At, W.conj())
+            Z = np.zeros(G.shape, dtype=np.complex128)
+            t_pre = time.perf_counter() - t0
+            nsamp = int(min(nt, max(2, 0.7 * budget_s / max(per_solve, 1e-3))))
+            t1 = time.perf_counter()
+            for k in range(nt - 1, nt - 1 - nsamp, -1):
+                rhs = G[:, k] - Ax @ (Z[:, k + 1:] @ S[k, k + 1:])
+                Z[:, k] = so._spatial_solve((Mx, Ax, S[k, k], rhs))
+            t_loop = (time.perf_counter() - t1) * nt / nsamp
+            t2 = time.perf_counter()
+            _ = (Z @ W.T).real
+            sec = t_pre + t_loop + (time.perf_counter() - t2)
+            sample = f"BSc steps 1, 2, 4 in full, {nsamp} of {nt} sequential spatial solves scaled to {nt}"
+    return {"value": dofs / sec, "unit": "DOF/s", "cores": 1, "kind": "oracle", "sample": sample, "seconds": sec}
 
 
 def run_batch(steps, warmup, precision):
@@ -419,6 +468,39 @@ def main():
         print(f"# cpu baseline: {cpu['value']:.3e} DOF/s on {cpu['cores']} cores ({cpu['sample']})",
               file=sys.stderr, flush=True)
 
+    # Algorithm BSc (FP64, N_t systems solved one after the other), where its
+    # N_t FP64 band factors fit comfortably
+    bsc = None
+    Mx0, Nt0 = res["fp64"]["Mx"], len(t) - 1
+    if Nt0 * Mx0 * (res["fp64"]["b"] + 1) * 16 <= 40e9:
+        bsteps, bwarm = max(1, min(args.steps, 3)), min(args.warmup, 1)
+        rb = run_gpu(loads, t, "fp64", bsteps, bwarm, method="bsc")
+        print(f"# bsc fp64: {rb['sec'] * 1e3:.2f} ms/step, iterations {rb['reps'][-1]['iterations']}, "
+              f"residual {rb['reps'][-1]['rel_residual'][-1]:.2e}", file=sys.stderr, flush=True)
+        bprof = rb["prof"]
+        bdom = max(bprof, key=lambda k: bprof[k][0])
+        bms, bn = bprof[bdom]
+        bavg = bms / max(bn, 1)
+        # a sequential sweep runs one system: its units are one system's bytes
+        bkind, bunits = stage_work(bdom, Mx0, Nt0, rb["b"], 1 if bdom.startswith("sweep") else Nt0,
+                                   spec["nrhs"], 8)
+        if bkind == "hbm":
+            broof = {"bound": "hbm", "achieved": bunits / (bavg * 1e-3) / 1e9, "peak": PEAK["hbm_GBs"],
+                     "unit": "GB/s"}
+        else:
+            broof = {"bound": "mfma", "achieved": bunits / (bavg * 1e-3) / 1e12, "peak": PEAK["fp64_mfma"],
+                     "unit": "TFLOP/s"}
+        broof.update(frac=broof["achieved"] / broof["peak"], traffic=None, kernel=bdom, avg_launch_ms=bavg,
+                     work_per_launch=bunits)
+        bsc = {"value": Mx0 * Nt0 * spec["nrhs"] / rb["sec"], "ms_per_step": rb["sec"] * 1e3, "steps": bsteps,
+               "iterations": rb["reps"][-1]["iterations"], "rel_residual": rb["reps"][-1]["rel_residual"][-1],
+               "setup_ms": rb["setup_s"] * 1e3, "roofline": broof,
+               "stages_ms_per_step": {k: v[0] / bsteps for k, v in bprof.items()}, "cpu_baseline": None}
+        if not args.no_cpu_baseline:
+            bsc["cpu_baseline"] = cpu_bsc(mesh, t, modes, args.cpu_budget)
+            print(f"# cpu baseline bsc: {bsc['cpu_baseline']['value']:.3e} DOF/s "
+                  f"({bsc['cpu_baseline']['sample']})", file=sys.stderr, flush=True)
+
     main_r = res["fp32"]
     Mx, Nt, nrhs = main_r["Mx"], len(t) - 1, spec["nrhs"]
     dofs = Mx * Nt * nrhs
@@ -496,6 +578,7 @@ def main():
         "setup_ms": main_r["setup_s"] * 1e3,
         "end_to_end_value": dofs / (main_r["sec"] + main_r["setup_s"]),
         "stages_ms_per_step": stages,
+        "bartels_stewart_bsc": bsc,
         "paper_cpu_fd": "1.68e6 DOF/s (48641 x 256 L-shape, 7.4 s, 2x Xeon E5-2687W v4, 24 cores, MATLAB+MUMPS)",
     }
     print(json.dumps(out))
