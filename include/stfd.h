@@ -174,6 +174,26 @@ int stfd_assemble_load(const stfd_space* s, int Nt, const double* Ct, const doub
                        double* Ftilde);
 
 /* ---------------------------------------------------------------------------
+ * Inhomogeneous Dirichlet data by homogenisation (Sec. 2 remark on Dirichlet
+ * data; used by the L-shape example of Sec. 5): the discrete extension
+ *   g_h(x, t) = sum over Dirichlet vertices v and k = 1..Nt of
+ *               G[v, k] psi_v(x) phi_k(t)
+ * (psi_v the P1 hat of vertex v, phi_k the time hats; g(., 0) = 0) is moved
+ * to the right-hand side,
+ *   Ftilde[i, l] -= sum_{v,k} (At[l,k] Mx[i,v] + Mt[l,k] Ax[i,v]) G[v, k],
+ * where Mx[i,v], Ax[i,v] couple interior node i to Dirichlet vertex v.  The
+ * discrete solution is then u_h = g_h + sum_{i,k} U[i,k] psi_i phi_k with U
+ * the solution for the updated Ftilde.
+ *   G     : nv*Nt column-major, G[v + nv*k] = g(x_v, t_{k+1}) (e.g. the
+ *           nodal interpolant); entries of interior vertices are not read.
+ *   At, Mt: row-major Nt*Nt as returned by stfd_assemble_time.
+ *   Ftilde: M_x*Nt column-major, updated in place (caller-owned).
+ * Host only.  Errors: STFD_EINVAL (null pointer, Nt < 1).
+ * ------------------------------------------------------------------------- */
+int stfd_dirichlet_lift(const stfd_space* s, int Nt, const double* At, const double* Mt,
+                        const double* G, double* Ftilde);
+
+/* ---------------------------------------------------------------------------
  * Steps 1a/1b of Algorithm FD on the host, for tests and reports.
  * Computes the generalised eigenvalues of (Mt, At) (Cholesky of At, Hessenberg
  * reduction, shifted QR), eigenvectors with unit 2-norm columns arranged as

@@ -17,9 +17,14 @@ Modules
   load            piecewise-constant projection Q_h^0 f and the assembled load
                   F~ = M^{1,0} F C_t^T (Sec. 2).
   solvers         the full Kronecker system K_h (Sec. 2, 3.1), the Fast
-                  Diagonalization algorithm (Sec. 4.4, Algorithm FD) and FP64
-                  iterative refinement on the K_h residual.
+                  Diagonalization algorithm (Sec. 4.4, Algorithm FD), the
+                  Bartels-Stewart algorithm with the complex Schur form
+                  (Sec. 4.3, Algorithm BSc) and FP64 iterative refinement on
+                  the K_h residual.
   errors          space-time L2(Q) and H1(Q) errors of a discrete solution.
+  lshape          the L-shape example of Sec. 5: its manufactured solution and
+                  source, the homogenisation of its Dirichlet data, and one
+                  table row (dof, mesh sizes, errors) per refinement level.
 
 Parity status of each function is stated in its docstring; every function is
 pinned by a test in ``tests/test_oracle_*.py`` against something other than

@@ -20,11 +20,14 @@ from .load import triangle_rule
 from .space_matrices import triangle_geometry
 
 
-def space_time_errors(mesh, t, U, u, grad_u, dt_u, n_space: int = 5, n_time: int = 4):
+def space_time_errors(mesh, t, U, u, grad_u, dt_u, n_space: int = 5, n_time: int = 4,
+                      boundary=None):
     """Return (L2(Q) error, H1(Q) seminorm error).
 
     u, dt_u: callables (x1, x2, t) -> value; grad_u: -> (g1, g2).
     U: (M_x, N_t) coefficients; node values at t_0 = 0 are zero.
+    boundary: None (zero Dirichlet data) or (nv, N_t) values at t_1..t_Nt of
+    the Dirichlet extension; only its rows for Dirichlet vertices are used.
     """
     xy = np.asarray(mesh.xy, dtype=np.float64)
     tri = np.asarray(mesh.tri, dtype=np.int64)
@@ -39,11 +42,13 @@ def space_time_errors(mesh, t, U, u, grad_u, dt_u, n_space: int = 5, n_time: int
     tg = 0.5 * (tg + 1)
     wg = 0.5 * wg
 
-    # nodal values per triangle vertex at every time node (zero on boundary
-    # and at t = 0)
+    # nodal values per triangle vertex at every time node (zero at t = 0;
+    # on the boundary zero or the given Dirichlet extension)
     Vfull = np.zeros((len(xy), nt + 1))
     inner = dof >= 0
     Vfull[inner, 1:] = U[dof[inner], :]
+    if boundary is not None:
+        Vfull[~inner, 1:] = np.asarray(boundary, dtype=np.float64)[~inner, :]
     err_l2 = 0.0
     err_h1 = 0.0
     for l in range(nt):

@@ -11,7 +11,8 @@ exact for polynomials of total degree 2n-2 (n = points per direction);
 time means are exact antiderivatives.
 
 Parity status: pinned by tests (rule exactness on monomials, doubling of
-the rule, the exact mean of a linear function).
+the rule, the exact mean of a linear function; for prism_means, the exact
+mean of a polynomial in x and t).
 """
 from __future__ import annotations
 
@@ -85,6 +86,27 @@ def manufactured_cell_means(mesh, t, n: int = 8):
     G = lambda s: s ** 2 + 2 * math.pi ** 2 * s ** 3 / 3
     st = (G(t[1:]) - G(t[:-1])) / h
     return np.outer(sx, st)
+
+
+def prism_means(mesh, t, f, n_space: int = 10, n_time: int = 12):
+    """F[j, l] = mean of f(x1, x2, t) over omega_j x (t_{l-1}, t_l) for a
+    general (not separable) f: the collapsed n_space x n_space rule on every
+    triangle times n_time-point Gauss-Legendre on every time element."""
+    xy = np.asarray(mesh.xy, dtype=np.float64)
+    tri = np.asarray(mesh.tri, dtype=np.int64)
+    t = np.asarray(t, dtype=np.float64)
+    l1, l2, wq = triangle_rule(n_space)
+    lam = np.stack([1 - l1 - l2, l1, l2], axis=1)              # (q, 3)
+    P = np.einsum("qa,jad->jqd", lam, xy[tri])                 # (ntri, q, 2)
+    tg, wg = np.polynomial.legendre.leggauss(n_time)
+    tg = 0.5 * (tg + 1)
+    wg = 0.5 * wg
+    F = np.zeros((len(tri), len(t) - 1))
+    for l in range(len(t) - 1):
+        h = t[l + 1] - t[l]
+        for tau, w in zip(tg, wg):
+            F[:, l] += w * (f(P[..., 0], P[..., 1], t[l] + tau * h) * wq[None, :]).sum(axis=1)
+    return F
 
 
 def assemble_load(M10, F, Ct):

@@ -19,6 +19,8 @@ of the hat products on a small mesh).
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import scipy.sparse as sp
 
@@ -80,3 +82,18 @@ def assemble(mesh):
     Ax.sum_duplicates()
     M10.sum_duplicates()
     return Mx, Ax, M10
+
+
+def boundary_coupling(mesh):
+    """(MB, AB): the entries M_x[i, v], A_x[i, v] of interior rows i against
+    Dirichlet vertices v, as (M_x, nv) CSR matrices indexed by vertex number
+    (columns of interior vertices are zero).  Same element matrices as
+    ``assemble``, with every vertex taken as a node."""
+    dof = np.asarray(mesh.dof, dtype=np.int64)
+    nv = len(dof)
+    every = dataclasses.replace(mesh, dof=np.arange(nv, dtype=np.int32))
+    Mf, Af, _ = assemble(every)
+    inner = np.where(dof >= 0)[0]
+    rows = inner[np.argsort(dof[inner])]                        # vertex of row i
+    keep = sp.diags((dof < 0).astype(np.float64))
+    return (Mf[rows] @ keep).tocsr(), (Af[rows] @ keep).tocsr()

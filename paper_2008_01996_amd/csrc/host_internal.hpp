@@ -18,6 +18,10 @@ struct stfd_space {
     // M10 (M_x x ntri, CSR)
     std::vector<int> rowptr10, col10;
     std::vector<double> val10;
+    // couplings of interior rows to Dirichlet vertices (M_x x nv, CSR over
+    // vertex numbers): the columns of M_x and A_x dropped for the boundary
+    std::vector<int> rowptrB, colB;
+    std::vector<double> valMB, valAB;
 };
 
 namespace stfd {

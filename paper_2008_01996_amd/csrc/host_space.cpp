@@ -71,6 +71,7 @@ extern "C" int stfd_space_create(int nv, const double* xy, int ntri, const int* 
     // element matrices: mass |T|/12 (1 + delta), stiffness |T| grad l_a . grad l_b
     std::vector<std::map<int, std::pair<double, double>>> rows(Mx);
     std::vector<std::map<int, double>> rows10(Mx);
+    std::vector<std::map<int, std::pair<double, double>>> rowsB(Mx);
     for (int e = 0; e < ntri; ++e) {
         int v[3];
         for (int a = 0; a < 3; ++a) {
@@ -93,8 +94,7 @@ extern "C" int stfd_space_create(int nv, const double* xy, int ntri, const int* 
             rows10[i][e] += area / 3.0;
             for (int b = 0; b < 3; ++b) {
                 const int j = dof[v[b]];
-                if (j < 0) continue;
-                auto& ent = rows[i][j];
+                auto& ent = j < 0 ? rowsB[i][v[b]] : rows[i][j];
                 ent.first += area / 12.0 * (a == b ? 2.0 : 1.0);
                 ent.second += area * (gx[a] * gx[b] + gy[a] * gy[b]);
             }
@@ -118,6 +118,15 @@ extern "C" int stfd_space_create(int nv, const double* xy, int ntri, const int* 
         }
     }
     s->half_band = hb;
+    s->rowptrB.assign(Mx + 1, 0);
+    for (int i = 0; i < Mx; ++i) {
+        s->rowptrB[i + 1] = s->rowptrB[i] + (int)rowsB[i].size();
+        for (auto& kv : rowsB[i]) {
+            s->colB.push_back(kv.first);
+            s->valMB.push_back(kv.second.first);
+            s->valAB.push_back(kv.second.second);
+        }
+    }
     *out = s;
     stfd::clear_error();
     return STFD_OK;
@@ -282,5 +291,38 @@ extern "C" int stfd_assemble_load(const stfd_space* s, int Nt, const double* Ct,
             for (int i = 0; i < i1 - i0; ++i) out[i] = acc[i];
         }
     }
+    return STFD_OK;
+}
+
+extern "C" int stfd_dirichlet_lift(const stfd_space* s, int Nt, const double* At, const double* Mt,
+                                   const double* G, double* Ft) {
+    if (!s || Nt < 1 || !At || !Mt || !G || !Ft) return fail(STFD_EINVAL, "dirichlet_lift: bad arguments");
+    const int Mx = s->Mx, nv = s->nv;
+    // only rows next to the boundary couple to it: P = M_B G, Q = A_B G on
+    // those rows, then Ft[i, l] -= sum_k P[i, k] At[l, k] + Q[i, k] Mt[l, k]
+    std::vector<int> brow;
+    for (int i = 0; i < Mx; ++i)
+        if (s->rowptrB[i + 1] > s->rowptrB[i]) brow.push_back(i);
+    const int nb = (int)brow.size();
+#pragma omp parallel for schedule(static)
+    for (int r = 0; r < nb; ++r) {
+        const int i = brow[r];
+        std::vector<double> P(Nt, 0.0), Q(Nt, 0.0);
+        for (int e = s->rowptrB[i]; e < s->rowptrB[i + 1]; ++e) {
+            const int v = s->colB[e];
+            for (int k = 0; k < Nt; ++k) {
+                const double g = G[(size_t)k * nv + v];
+                P[k] += s->valMB[e] * g;
+                Q[k] += s->valAB[e] * g;
+            }
+        }
+        for (int l = 0; l < Nt; ++l) {
+            double acc = 0.0;
+            for (int k = 0; k < Nt; ++k)
+                acc += P[k] * At[(size_t)l * Nt + k] + Q[k] * Mt[(size_t)l * Nt + k];
+            Ft[(size_t)l * Mx + i] -= acc;
+        }
+    }
+    stfd::clear_error();
     return STFD_OK;
 }

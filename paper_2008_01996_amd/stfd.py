@@ -23,7 +23,7 @@ MAX_HIST = 64
 EXPORTED = [
     "stfd_opts_default", "stfd_last_error", "stfd_assemble_time", "stfd_space_create",
     "stfd_space_free", "stfd_space_info", "stfd_space_csr_size", "stfd_space_export_csr",
-    "stfd_project_f", "stfd_assemble_load", "stfd_time_decompose", "stfd_time_schur", "stfd_fd_setup",
+    "stfd_project_f", "stfd_assemble_load", "stfd_dirichlet_lift", "stfd_time_decompose", "stfd_time_schur", "stfd_fd_setup",
     "stfd_fd_setup_report", "stfd_fd_factor", "stfd_fd_solve", "stfd_kh_residual",
     "stfd_problem_free", "stfd_fd_apply", "stfd_spatial_solve", "stfd_system_lambdas",
     "stfd_profile", "stfd_profile_read", "stfd_batch_create", "stfd_batch_factor", "stfd_batch_solve",
@@ -94,6 +94,7 @@ def lib():
         L.stfd_space_export_csr.argtypes = [vp, C.c_int, ip, ip, dp]
         L.stfd_project_f.argtypes = [vp, C.c_int, dp, C.c_int, C.c_int, ip, ip, ip, dp, dp, dp]
         L.stfd_assemble_load.argtypes = [vp, C.c_int, dp, dp, dp]
+        L.stfd_dirichlet_lift.argtypes = [vp, C.c_int, dp, dp, dp, dp]
         L.stfd_time_decompose.argtypes = [C.c_int, dp, dp, dp, dp, dp, dp, dp, C.POINTER(SetupReport)]
         L.stfd_time_schur.argtypes = [C.c_int, dp, dp, dp, dp]
         L.stfd_fd_setup.argtypes = [vp, C.c_int, dp, dp, C.POINTER(Opts), vp, C.POINTER(vp)]
@@ -185,6 +186,7 @@ class Space:
         nnz = C.c_longlong()
         _check(lib().stfd_space_info(self._h, C.byref(mx), C.byref(nt), C.byref(hb), C.byref(nnz)))
         self.Mx, self.ntri, self.half_band, self.nnz = mx.value, nt.value, hb.value, nnz.value
+        self.nv = len(dof)
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -224,6 +226,20 @@ class Space:
         Fc = np.ascontiguousarray(np.asarray(F, dtype=np.float64).T)      # column-major
         out = np.empty((nt, self.Mx))
         _check(lib().stfd_assemble_load(self._h, nt, _dp(Ct), _dp(Fc), _dp(out)))
+        return out.T
+
+    def dirichlet_lift(self, At, Mt, G, Ft):
+        """Ft - (the coupling of the Dirichlet extension with nodal values
+        G[v, k] at vertex v and time t_{k+1}) as a new (M_x, N_t) array;
+        rows of G for interior vertices are ignored."""
+        At = _f64(At)
+        Mt = _f64(Mt)
+        nt = At.shape[0]
+        Gc = np.ascontiguousarray(np.asarray(G, dtype=np.float64).T)      # column-major nv x Nt
+        out = np.ascontiguousarray(np.asarray(Ft, dtype=np.float64).T)    # column-major M_x x Nt
+        if Gc.shape != (nt, self.nv) or out.shape != (nt, self.Mx) or Mt.shape != (nt, nt):
+            raise ValueError("dirichlet_lift: shape mismatch")
+        _check(lib().stfd_dirichlet_lift(self._h, nt, _dp(At), _dp(Mt), _dp(Gc), _dp(out)))
         return out.T
 
 

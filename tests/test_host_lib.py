@@ -87,6 +87,31 @@ def test_load_matches_oracle(kind):
     assert np.abs(Ft - Fto).max() <= 1e-13 * np.abs(Fto).max()
 
 
+@pytest.mark.parametrize("diagonal", ["sw-ne", "nw-se"])
+def test_dirichlet_lift_matches_oracle(diagonal):
+    """Homogenisation of inhomogeneous Dirichlet data (the L-shape example of
+    Sec. 5): the library's update of F~ against the oracle's coupling term
+    M_B G A_t^T + A_B G M_t^T for the manufactured solution's data."""
+    from oracle import lshape as ls
+    mesh = w.lshape_mesh(16, diagonal=diagonal)
+    t = w.paper_times(2)
+    At, Mt, _ = tm.kernel(t)
+    MB, AB = sm.boundary_coupling(mesh)
+    G = ls.dirichlet_values(mesh, t)
+    rng = np.random.Generator(np.random.PCG64(4100))
+    sp = stfd.Space(mesh)
+    Ft = rng.standard_normal((sp.Mx, len(t) - 1))
+    want = Ft - ls.lift(MB, AB, At, Mt, G)
+    got = sp.dirichlet_lift(At, Mt, G, Ft)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+    # interior rows of G are not read
+    G2 = G.copy()
+    G2[mesh.dof >= 0] = np.nan
+    assert np.array_equal(sp.dirichlet_lift(At, Mt, G2, Ft), got)
+    with pytest.raises(ValueError):
+        sp.dirichlet_lift(At, Mt, G[:, :-1], Ft)
+
+
 def _match(a, b):
     """max distance of a matching of two eigenvalue lists (greedy nearest)."""
     b = list(b)

@@ -11,7 +11,7 @@ shapes are the unit-square problems the GPU benchmark is quoted on):
 
 * ``square_mesh(nc)``: unit square, ``nc`` cells per side, each cell cut along
   its SW-NE diagonal.  Interior nodes are numbered row by row, x fastest.
-* ``lshape_mesh(nc)``: (-1,1)^2 minus [0,1]x[-1,0] on the same kind of grid
+* ``lshape_mesh(nc, diagonal)``: (-1,1)^2 minus [0,1]x[-1,0] on the same kind of grid
   with ``nc`` cells per side of the big square (mesh size 2/nc).
 * ``uniform_times``, ``graded_times``, ``paper_times``: time partitions.
 * ``random_modes``: the eight separable sine/cosine modes of the random
@@ -51,7 +51,9 @@ class Mesh:
         return int((self.dof >= 0).sum())
 
 
-def _grid_mesh(nc: int, lo: float, hi: float, keep_cell) -> Mesh:
+def _grid_mesh(nc: int, lo: float, hi: float, keep_cell, diagonal: str = "sw-ne") -> Mesh:
+    if diagonal not in ("sw-ne", "nw-se"):
+        raise ValueError("diagonal must be 'sw-ne' or 'nw-se'")
     h = (hi - lo) / nc
     n1 = nc + 1
     ii, jj = np.meshgrid(np.arange(n1), np.arange(n1), indexing="xy")
@@ -67,9 +69,14 @@ def _grid_mesh(nc: int, lo: float, hi: float, keep_cell) -> Mesh:
             v10 = v00 + 1
             v01 = v00 + n1
             v11 = v01 + 1
-            # SW-NE diagonal: lower-right and upper-left triangles
-            tris.append((v00, v10, v11))
-            tris.append((v00, v11, v01))
+            if diagonal == "sw-ne":
+                # lower-right and upper-left triangles
+                tris.append((v00, v10, v11))
+                tris.append((v00, v11, v01))
+            else:
+                # NW-SE diagonal: lower-left and upper-right triangles
+                tris.append((v00, v10, v01))
+                tris.append((v10, v11, v01))
             used[[v00, v10, v01, v11]] = True
     tri_all = np.asarray(tris, dtype=np.int64)
 
@@ -119,15 +126,17 @@ def rect_mesh(ncx: int, ncy: int) -> Mesh:
     return Mesh(xy=m.xy, tri=m.tri, dof=m.dof, h=h, rows=m.rows, box=(0.0, ncx * h, 0.0, 1.0))
 
 
-def lshape_mesh(nc: int) -> Mesh:
+def lshape_mesh(nc: int, diagonal: str = "sw-ne") -> Mesh:
     """L-shape (-1,1)^2 minus [0,1]x[-1,0]; nc even cells per side, h = 2/nc.
 
     This is the spatial domain of the paper's numerical example (Sec. 5).
+    ``diagonal`` picks the cut of every square cell: "sw-ne" (default) or
+    "nw-se".
     """
     if nc < 2 or nc % 2:
         raise ValueError("nc must be even and >= 2")
     half = nc // 2
-    return _grid_mesh(nc, -1.0, 1.0, lambda i, j: not (i >= half and j < half))
+    return _grid_mesh(nc, -1.0, 1.0, lambda i, j: not (i >= half and j < half), diagonal)
 
 
 def uniform_times(nt: int, T: float = 1.0) -> np.ndarray:
