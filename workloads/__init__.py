@@ -209,7 +209,7 @@ MANUFACTURED = "sin(pi x1) sin(pi x2) t^2"
 
 def rhs_seeds(config: str, nrhs: int, problem: int = 0) -> list[int]:
     """Seeds of the random right-hand sides of each configuration."""
-    base = {"square256_nt512": 3000, "batch": 4000, "lshape_nt1024": 5000}[config]
+    base = {"square256_nt512": 3000, "batch": 4000, "lshape_nt1024": 5000, "lshape_paper": 6000}[config]
     if config == "batch":
         return [base + 8 * problem + r for r in range(nrhs)]
     return [base + r for r in range(nrhs)]
