@@ -124,6 +124,13 @@ static inline void givens(cd x, cd y, double& c, cd& s) {
 // Single-shift complex QR on an upper Hessenberg matrix, full Schur form
 // T = Z^H H Z accumulated into z.  Wilkinson shifts, exceptional shifts every
 // ten iterations without deflation.
+//
+// A sweep's rotations act on the column pairs (k, k+1) of H and Z.  The
+// bulge chase only reads rows k-1..k+2 of H again, so the column rotations
+// of the rows above (and all of Z, which it never reads) are kept and applied
+// after the sweep, row by row: each row then walks its rotations in order
+// over contiguous memory, and the rows run in parallel.  Every entry sees the
+// same operations in the same order as with immediate updates.
 // ---------------------------------------------------------------------------
 static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::string* err) {
     const double eps = std::numeric_limits<double>::epsilon();
@@ -132,6 +139,8 @@ static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::st
     const double small = std::max(hnorm, 1.0) * std::numeric_limits<double>::min() / eps;
     int ihi = n - 1;
     int iter = 0, total = 0;
+    std::vector<double> rot_c(n);
+    std::vector<cd> rot_s(n);
     while (ihi > 0) {
         int l = ihi;
         for (; l > 0; --l) {
@@ -179,6 +188,8 @@ static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::st
             double cs;
             cd sn;
             givens(x, y, cs, sn);
+            rot_c[k] = cs;
+            rot_s[k] = sn;
             // rows k, k+1 from column max(k-1, l) to n-1
             const int j0 = (k > l) ? k - 1 : l;
             cd* rk = &h[(size_t)k * n];
@@ -189,20 +200,38 @@ static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::st
                 rk1[j] = -std::conj(sn) * u + cs * v;
             }
             if (k > l) h[(size_t)(k + 1) * n + k - 1] = 0.0;
-            // columns k, k+1 (times G^H) for rows 0..min(k+2, ihi)
+            // columns k, k+1 (times G^H) for the rows the chase reads again,
+            // max(0, k-1)..min(k+2, ihi); rows 0..k-2 follow after the sweep
             const int i1 = std::min(k + 2, ihi);
             const cd snc = std::conj(sn);
-            for (int i = 0; i <= i1; ++i) {
+            for (int i = std::max(0, k - 1); i <= i1; ++i) {
                 cd* ri = &h[(size_t)i * n];
                 const cd u = ri[k], v = ri[k + 1];
                 ri[k] = cs * u + snc * v;
                 ri[k + 1] = -sn * u + cs * v;
             }
-            for (int i = 0; i < n; ++i) {
-                cd* zi = &z[(size_t)i * n];
+        }
+        // the deferred column rotations: row i of H takes those of steps
+        // k >= max(l, i+2), every row of Z those of all steps l..ihi-1
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            cd* zi = &z[(size_t)i * n];
+            for (int k = l; k < ihi; ++k) {
+                const double cs = rot_c[k];
+                const cd sn = rot_s[k], snc = std::conj(sn);
                 const cd u = zi[k], v = zi[k + 1];
                 zi[k] = cs * u + snc * v;
                 zi[k + 1] = -sn * u + cs * v;
+            }
+            if (i + 2 < ihi) {
+                cd* ri = &h[(size_t)i * n];
+                for (int k = std::max(l, i + 2); k < ihi; ++k) {
+                    const double cs = rot_c[k];
+                    const cd sn = rot_s[k], snc = std::conj(sn);
+                    const cd u = ri[k], v = ri[k + 1];
+                    ri[k] = cs * u + snc * v;
+                    ri[k + 1] = -sn * u + cs * v;
+                }
             }
         }
     }
@@ -362,6 +391,39 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
         }
     }
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// max_k ||(M - lam_k A) x_k||_inf / ((||M||_inf + |lam_k| ||A||_inf) ||x_k||_inf)
+// for real row-major A, M and the columns x_k of a row-major complex X.
+// ---------------------------------------------------------------------------
+double eig_residual(int n, const double* A, const double* M, const std::vector<cd>& lam,
+                    const std::vector<cd>& X) {
+    double nA = 0.0, nM = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double ra = 0.0, rm = 0.0;
+        for (int j = 0; j < n; ++j) {
+            ra += std::fabs(A[(size_t)i * n + j]);
+            rm += std::fabs(M[(size_t)i * n + j]);
+        }
+        nA = std::max(nA, ra);
+        nM = std::max(nM, rm);
+    }
+    double res = 0.0;
+#pragma omp parallel for schedule(dynamic, 8) reduction(max : res)
+    for (int k = 0; k < n; ++k) {
+        std::vector<cd> x(n);
+        for (int j = 0; j < n; ++j) x[j] = X[(size_t)j * n + k];
+        double r = 0.0, xn = 0.0;
+        for (int i = 0; i < n; ++i) {
+            cd s = 0.0;
+            for (int j = 0; j < n; ++j) s += (M[(size_t)i * n + j] - lam[k] * A[(size_t)i * n + j]) * x[j];
+            r = std::max(r, std::abs(s));
+            xn = std::max(xn, std::abs(x[i]));
+        }
+        res = std::max(res, r / ((nM + std::abs(lam[k]) * nA) * xn));
+    }
+    return res;
 }
 
 }  // namespace stfd

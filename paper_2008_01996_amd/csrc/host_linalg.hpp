@@ -37,6 +37,12 @@ bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<
 // not converge.
 bool schur_real(int n, std::vector<double>& a, std::vector<cd>& t, std::vector<cd>& z, std::string* err);
 
+// Relative eigen residual of the pencil (M, A) (real row-major n x n) for the
+// eigenvalues lam and the columns of X (row-major n x n):
+// max_k ||(M - lam_k A) x_k||_inf / ((||M||_inf + |lam_k| ||A||_inf) ||x_k||_inf).
+double eig_residual(int n, const double* A, const double* M, const std::vector<cd>& lam,
+                    const std::vector<cd>& X);
+
 // One-sided Jacobi SVD of a complex n x n matrix: a = U diag(s) V^H.
 // a is row-major and destroyed; U, V row-major; s descending.
 bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,

@@ -223,27 +223,7 @@ int decompose(int n, const double* At, const double* Mt, Decomp& D) {
         for (int i = 0; i < n; ++i) D.X[(size_t)i * n + k] = x[i].real() / nrm;
     }
     // eigen residual  ||M x - lam A x|| / ((||M|| + |lam| ||A||) ||x||)
-    double nA = 0.0, nM = 0.0;
-    for (int i = 0; i < n; ++i) {
-        double ra = 0.0, rm = 0.0;
-        for (int j = 0; j < n; ++j) {
-            ra += std::fabs(At[(size_t)i * n + j]);
-            rm += std::fabs(Mt[(size_t)i * n + j]);
-        }
-        nA = std::max(nA, ra);
-        nM = std::max(nM, rm);
-    }
-    D.eig_res = 0.0;
-    for (int k = 0; k < n; ++k) {
-        double r = 0.0, xn = 0.0;
-        for (int i = 0; i < n; ++i) {
-            cd s = 0.0;
-            for (int j = 0; j < n; ++j) s += (Mt[(size_t)i * n + j] - D.lam[k] * At[(size_t)i * n + j]) * D.X[(size_t)j * n + k];
-            r = std::max(r, std::abs(s));
-            xn = std::max(xn, std::abs(D.X[(size_t)i * n + k]));
-        }
-        D.eig_res = std::max(D.eig_res, r / ((nM + std::abs(D.lam[k]) * nA) * xn));
-    }
+    D.eig_res = stfd::eig_residual(n, At, Mt, D.lam, D.X);
     for (auto& l : D.lam)
         if (!(l.real() > 0.0)) return fail(STFD_ENUMERIC, "an eigenvalue of (M_t, A_t) has Re <= 0");
     std::vector<cd> Xw = D.X;
