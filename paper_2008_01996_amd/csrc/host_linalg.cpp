@@ -303,7 +303,11 @@ bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<
 // One-sided (Hestenes) Jacobi SVD.  Columns of a are orthogonalised by plane
 // rotations applied on the right; V accumulates the rotations.  Pairs are
 // visited in a round-robin tournament so that each round's rotations are
-// independent.
+// independent.  Columns are kept column-major with separate real and
+// imaginary parts (the loops over a column vectorise), and the squared
+// column norms are carried through each sweep by the rotation's closed form
+// (||a_p||^2 - t g, ||a_q||^2 + t g) and recomputed at the start of the next,
+// so that a pair needs one complex inner product.
 // ---------------------------------------------------------------------------
 bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
                 std::vector<cd>& V, std::string* err) {
@@ -311,16 +315,27 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
     // rotation threshold on the cosine between two columns: sqrt(n) eps, the
     // level the rounding of the column inner products allows
     const double tol = std::sqrt((double)n) * eps;
-    // work column-major for contiguous column access
-    std::vector<cd> A((size_t)n * n), W((size_t)n * n, 0.0);
+    const size_t nn = (size_t)n * n;
+    std::vector<double> Ar(nn), Ai(nn), Wr(nn, 0.0), Wi(nn, 0.0), nrm(n);
     for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) A[(size_t)j * n + i] = a[(size_t)i * n + j];
-    for (int j = 0; j < n; ++j) W[(size_t)j * n + j] = 1.0;
+        for (int j = 0; j < n; ++j) {
+            Ar[(size_t)j * n + i] = a[(size_t)i * n + j].real();
+            Ai[(size_t)j * n + i] = a[(size_t)i * n + j].imag();
+        }
+    for (int j = 0; j < n; ++j) Wr[(size_t)j * n + j] = 1.0;
     const int m = n + (n & 1);            // tournament size (pad with a dummy)
     std::vector<int> ring(m);
     for (int i = 0; i < m; ++i) ring[i] = i;
     bool converged = false;
     for (int sweep = 0; sweep < 60 && !converged; ++sweep) {
+#pragma omp parallel for schedule(static)
+        for (int j = 0; j < n; ++j) {
+            const double* xr = &Ar[(size_t)j * n];
+            const double* xi = &Ai[(size_t)j * n];
+            double t = 0.0;
+            for (int i = 0; i < n; ++i) t += xr[i] * xr[i] + xi[i] * xi[i];
+            nrm[j] = t;
+        }
         double off = 0.0;
         for (int round = 0; round < m - 1; ++round) {
 #pragma omp parallel for schedule(static) reduction(max : off)
@@ -328,35 +343,49 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
                 int p = ring[pidx], q = ring[m - 1 - pidx];
                 if (p >= n || q >= n) continue;
                 if (p > q) std::swap(p, q);
-                cd* ap = &A[(size_t)p * n];
-                cd* aq = &A[(size_t)q * n];
-                double al = 0.0, be = 0.0;
-                cd ga = 0.0;
+                double* pr = &Ar[(size_t)p * n];
+                double* pi = &Ai[(size_t)p * n];
+                double* qr = &Ar[(size_t)q * n];
+                double* qi = &Ai[(size_t)q * n];
+                const double al = nrm[p], be = nrm[q];
+                // ga = <a_p, a_q> = sum conj(a_p) a_q
+                double gr = 0.0, gi = 0.0;
                 for (int i = 0; i < n; ++i) {
-                    al += std::norm(ap[i]);
-                    be += std::norm(aq[i]);
-                    ga += std::conj(ap[i]) * aq[i];
+                    gr += pr[i] * qr[i] + pi[i] * qi[i];
+                    gi += pr[i] * qi[i] - pi[i] * qr[i];
                 }
-                const double g = std::abs(ga);
+                const double g = std::hypot(gr, gi);
                 if (g == 0.0 || g <= tol * std::sqrt(al * be)) continue;
                 off = std::max(off, g / std::sqrt(al * be));
                 // D = diag(1, e^{-i phi}) makes the Gram matrix real; then a
                 // real Jacobi rotation diagonalises it
-                const cd ph = std::conj(ga) / g;             // e^{-i phi}
+                const double phr = gr / g, phi = -gi / g;          // e^{-i phi} = conj(ga) / |ga|
                 const double zeta = (be - al) / (2.0 * g);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
                 const double c = 1.0 / std::sqrt(1.0 + t * t);
                 const double sn = c * t;
-                cd* wp = &W[(size_t)p * n];
-                cd* wq = &W[(size_t)q * n];
                 for (int i = 0; i < n; ++i) {
-                    const cd x = ap[i], y = ph * aq[i];
-                    ap[i] = c * x - sn * y;
-                    aq[i] = sn * x + c * y;
-                    const cd xv = wp[i], yv = ph * wq[i];
-                    wp[i] = c * xv - sn * yv;
-                    wq[i] = sn * xv + c * yv;
+                    const double xr = pr[i], xi = pi[i];
+                    const double yr = phr * qr[i] - phi * qi[i], yi = phr * qi[i] + phi * qr[i];
+                    pr[i] = c * xr - sn * yr;
+                    pi[i] = c * xi - sn * yi;
+                    qr[i] = sn * xr + c * yr;
+                    qi[i] = sn * xi + c * yi;
                 }
+                double* wpr = &Wr[(size_t)p * n];
+                double* wpi = &Wi[(size_t)p * n];
+                double* wqr = &Wr[(size_t)q * n];
+                double* wqi = &Wi[(size_t)q * n];
+                for (int i = 0; i < n; ++i) {
+                    const double xr = wpr[i], xi = wpi[i];
+                    const double yr = phr * wqr[i] - phi * wqi[i], yi = phr * wqi[i] + phi * wqr[i];
+                    wpr[i] = c * xr - sn * yr;
+                    wpi[i] = c * xi - sn * yi;
+                    wqr[i] = sn * xr + c * yr;
+                    wqi[i] = sn * xi + c * yi;
+                }
+                nrm[p] = al - t * g;
+                nrm[q] = be + t * g;
             }
             // rotate the tournament (element 0 fixed)
             const int last = ring[m - 1];
@@ -372,22 +401,22 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
     std::vector<double> sv(n);
     for (int j = 0; j < n; ++j) {
         double t = 0.0;
-        for (int i = 0; i < n; ++i) t += std::norm(A[(size_t)j * n + i]);
+        for (int i = 0; i < n; ++i) t += Ar[(size_t)j * n + i] * Ar[(size_t)j * n + i] + Ai[(size_t)j * n + i] * Ai[(size_t)j * n + i];
         sv[j] = std::sqrt(t);
     }
     std::vector<int> order(n);
     for (int j = 0; j < n; ++j) order[j] = j;
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return sv[x] > sv[y]; });
     s.resize(n);
-    U.assign((size_t)n * n, 0.0);
-    V.assign((size_t)n * n, 0.0);
+    U.assign(nn, 0.0);
+    V.assign(nn, 0.0);
     for (int jj = 0; jj < n; ++jj) {
         const int j = order[jj];
         s[jj] = sv[j];
         const double inv = sv[j] > 0 ? 1.0 / sv[j] : 0.0;
         for (int i = 0; i < n; ++i) {
-            U[(size_t)i * n + jj] = A[(size_t)j * n + i] * inv;
-            V[(size_t)i * n + jj] = W[(size_t)j * n + i];
+            U[(size_t)i * n + jj] = cd(Ar[(size_t)j * n + i], Ai[(size_t)j * n + i]) * inv;
+            V[(size_t)i * n + jj] = cd(Wr[(size_t)j * n + i], Wi[(size_t)j * n + i]);
         }
     }
     return true;
