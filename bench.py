@@ -47,8 +47,8 @@ FP64_STAGES_IN_FP32_FORM = ("fwd1", "back", "resid")
 # size), keyed by the SHA-256 of the kernel's source file: a changed source
 # reports traffic as null until the counters are taken again.
 TRAFFIC = {
-    # band_ldl_reg_kernel, square128_nt256: FETCH 1.156569e6 KiB x 1.9997 + WRITE 2.081206e6 KiB x 1.0
-    ("square128_nt256", "band_ldl"): {"source_sha256": "a38814f1e66c0f7c7c10127a076270df2baa650bdea745c7344342f5f16ba042", "bytes_per_launch": 4.4995e9},
+    # band_ldl_reg_kernel, square128_nt256: FETCH 1.186736e6 KiB x 1.9998 + WRITE 2.081217e6 KiB x 1.0
+    ("square128_nt256", "band_ldl"): {"source_sha256": "a38814f1e66c0f7c7c10127a076270df2baa650bdea745c7344342f5f16ba042", "bytes_per_launch": 4.5613e+09},
 }
 
 WORKLOADS = {
