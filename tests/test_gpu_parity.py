@@ -369,6 +369,18 @@ def test_fp64_transform_variants(mask):
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_large_space_with_ragged_tiles(precision):
+    """M_x = 33124: a ragged last GEMM tile (33124 = 517 * 64 + 36), a padded
+    half-bandwidth of 192 (183 nodes per row), two right-hand sides."""
+    mesh = w.square_mesh(183)
+    t = w.uniform_times(6)
+    At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[7300, 7301])
+    assert Mx.shape[0] == 33124
+    Us, rep, _ = _gpu_solve(stfd.Space(mesh), At, Mt, Fs, precision)
+    _check(At, Mt, Mx, Ax, Fs, Us, rep)
+
+
 def test_solve_is_deterministic():
     mesh = w.square_mesh(16)
     t = w.uniform_times(16)
