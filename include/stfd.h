@@ -161,6 +161,10 @@ int stfd_space_export_csr(const stfd_space* s, int which, int* rowptr, int* col,
  *   kind 1: f = sum_q c_q sin(a_q pi xi1) sin(b_q pi xi2) (2t + 2 pi^2 t^2)
  *           (kind 1 with a = b = 1, c = 1 on the unit square is the load of
  *           u = sin(pi x1) sin(pi x2) t^2)
+ *   kind 2: the source of the L-shape example of Sec. 5, f = u_t - Laplace u
+ *           for u = 5/(2 pi t) exp(-|x - c|^2/(4t)) sin(pi x1 x2),
+ *           c = (1/4, -1/4); the mode arguments and box are not read (may be
+ *           NULL) and time means use 12-point Gauss-Legendre per element
  * with xi = (x - (xmin, ymin)) / (xmax - xmin, ymax - ymin) and box =
  * {xmin, xmax, ymin, ymax}.  Space means use a 10x10 collapsed Gauss rule per
  * triangle, time means are exact.  F: caller-owned Ntri*Nt, column-major.

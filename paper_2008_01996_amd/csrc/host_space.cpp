@@ -199,13 +199,67 @@ void gauss01(int n, std::vector<double>& x, std::vector<double>& w) {
 
 }  // namespace
 
+// Source of the L-shape example of Sec. 5: u = G sin(pi x1 x2) with
+// G = 5/(2 pi t) exp(-|x - c|^2/(4t)), c = (1/4, -1/4), and G_t = Laplace G
+// (ten times the heat kernel), so f = u_t - Laplace u = -2 grad G . grad s
+// - G Laplace s = G [pi cos(pi x1 x2) ((x1 - c1) x2 + (x2 - c2) x1) / t
+// + pi^2 (x1^2 + x2^2) sin(pi x1 x2)].
+static inline double lshape_source(double x1, double x2, double t) {
+    const double c1 = 0.25, c2 = -0.25;
+    const double r2 = (x1 - c1) * (x1 - c1) + (x2 - c2) * (x2 - c2);
+    const double G = 5.0 / (2.0 * kPi * t) * std::exp(-r2 / (4.0 * t));
+    const double sn = std::sin(kPi * x1 * x2), cs = std::cos(kPi * x1 * x2);
+    return G * (kPi * cs * ((x1 - c1) * x2 + (x2 - c2) * x1) / t + kPi * kPi * (x1 * x1 + x2 * x2) * sn);
+}
+
+// Prism means of the Sec. 5 source: the 10 x 10 collapsed triangle rule
+// times 12-point Gauss-Legendre on every time element.
+static void project_lshape_source(const stfd_space* s, int Nt, const double* t, double* F) {
+    const int n = 10, nt = 12;
+    std::vector<double> gx, gw, tx, tw;
+    gauss01(n, gx, gw);
+    gauss01(nt, tx, tw);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < s->ntri; ++e) {
+        const int* v = &s->tri[3 * (size_t)e];
+        const double p0x = s->xy[2 * v[0]], p0y = s->xy[2 * v[0] + 1];
+        const double p1x = s->xy[2 * v[1]], p1y = s->xy[2 * v[1] + 1];
+        const double p2x = s->xy[2 * v[2]], p2y = s->xy[2 * v[2] + 1];
+        double px[100], py[100], pw[100];
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double u = gx[i], vv = gx[j];
+                px[i * n + j] = p2x + u * (p0x - p2x) + u * vv * (p1x - p0x);
+                py[i * n + j] = p2y + u * (p0y - p2y) + u * vv * (p1y - p0y);
+                pw[i * n + j] = gw[i] * gw[j] * 2.0 * u;
+            }
+        for (int l = 0; l < Nt; ++l) {
+            const double t0 = t[l], h = t[l + 1] - t[l];
+            double acc = 0.0;
+            for (int k = 0; k < nt; ++k) {
+                const double tk = t0 + tx[k] * h;
+                double sk = 0.0;
+                for (int q = 0; q < n * n; ++q) sk += pw[q] * lshape_source(px[q], py[q], tk);
+                acc += tw[k] * sk;
+            }
+            F[(size_t)l * s->ntri + e] = acc;
+        }
+    }
+}
+
 extern "C" int stfd_project_f(const stfd_space* s, int Nt, const double* t, int kind, int nmodes, const int* a,
                               const int* b, const int* d, const double* c, const double* box, double* F) {
-    if (!s || Nt < 1 || !t || nmodes < 1 || !a || !b || !c || !box || !F || (kind != 0 && kind != 1) ||
-        (kind == 0 && !d))
+    if (!s || Nt < 1 || !t || !F || kind < 0 || kind > 2)
+        return fail(STFD_EINVAL, "project_f: bad arguments");
+    if (kind != 2 && (nmodes < 1 || !a || !b || !c || !box || (kind == 0 && !d)))
         return fail(STFD_EINVAL, "project_f: bad arguments");
     for (int l = 0; l < Nt; ++l)
         if (!(t[l + 1] > t[l])) return fail(STFD_EINVAL, "project_f: t must increase");
+    if (kind == 2) {
+        if (!(t[0] >= 0.0)) return fail(STFD_EINVAL, "project_f: kind 2 needs t[0] >= 0");
+        project_lshape_source(s, Nt, t, F);
+        return STFD_OK;
+    }
     const double T = t[Nt];
     const double bx = box[1] - box[0], by = box[3] - box[2];
     if (!(bx > 0) || !(by > 0)) return fail(STFD_EINVAL, "project_f: empty box");

@@ -205,11 +205,16 @@ class Space:
         _check(lib().stfd_space_export_csr(self._h, which, _ip(rp), _ip(cl), _dp(vl)))
         return rp, cl, vl, (r.value, c.value)
 
-    def project_f(self, t, modes, kind=0):
-        """Prism means F (ntri x Nt) of a separable f (kind 0: random modes,
-        kind 1: manufactured time profile 2t + 2 pi^2 t^2)."""
+    def project_f(self, t, modes=None, kind=0):
+        """Prism means F (ntri x Nt) of f: kind 0 random modes, kind 1 the
+        manufactured time profile 2t + 2 pi^2 t^2, kind 2 the source of the
+        L-shape example of Sec. 5 (modes not used)."""
         t = _f64(t)
         nt = len(t) - 1
+        if kind == 2:
+            F = np.empty((nt, self.ntri))
+            _check(lib().stfd_project_f(self._h, nt, _dp(t), 2, 0, None, None, None, None, None, _dp(F)))
+            return F.T
         a = np.ascontiguousarray(modes.a, np.int32)
         b = np.ascontiguousarray(modes.b, np.int32)
         d = np.ascontiguousarray(modes.d, np.int32)

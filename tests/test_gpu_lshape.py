@@ -70,6 +70,30 @@ def test_lshape_level_matches_oracle(level, method, precision):
     assert abs(l2 / l2o - 1) <= 1e-8 and abs(h1 / h1o - 1) <= 1e-8
 
 
+@pytest.mark.parametrize("level", [0, 2, 3])
+def test_lshape_through_the_library_alone(level):
+    """The example with nothing computed outside the library but the
+    Dirichlet values: the source's prism means by project_f kind 2, the load,
+    the lift and the FP32 + refinement solve.  The load differs from the
+    oracle's by its quadrature (<= 1e-5 of max |F|), so the error norms agree
+    with the oracle's to 1e-5 (measured <= 6.2e-7 with the oracle's own
+    solver on the same load) rather than to the solver's 1e-10."""
+    case, _, (l2o, h1o) = _oracle_level(level)
+    sp = stfd.Space(case["mesh"])
+    At, Mt, Ct = stfd.assemble_time(case["t"])
+    Ft = sp.dirichlet_lift(At, Mt, case["G"], sp.assemble_load(Ct, sp.project_f(case["t"], kind=2)))
+    prob = stfd.Problem(sp, At, Mt, precision="fp32", rtol=1e-11)
+    prob.factor()
+    F = torch.from_numpy(np.ascontiguousarray(Ft.T[None])).to("cuda:0")
+    U = torch.empty_like(F)
+    rep = prob.solve(F, U)
+    torch.cuda.synchronize()
+    assert rep["converged"], rep
+    l2, h1 = ls.errors(case, U.cpu().numpy()[0].T.copy())
+    print(f"  level {level}: L2 {l2:.5e} (oracle {l2o:.5e})  H1 {h1:.5e} (oracle {h1o:.5e})")
+    assert abs(l2 / l2o - 1) <= 1e-5 and abs(h1 / h1o - 1) <= 1e-5
+
+
 def test_lshape_convergence_orders_on_the_gpu():
     """Observed orders between levels 3 and 4 of the FP32 + refinement
     solutions: about 2 in L2(Q) and 1 in the H1(Q) seminorm."""

@@ -87,6 +87,21 @@ def test_load_matches_oracle(kind):
     assert np.abs(Ft - Fto).max() <= 1e-13 * np.abs(Fto).max()
 
 
+@pytest.mark.parametrize("level", [0, 1, 2])
+def test_lshape_source_means_match_oracle(level):
+    """Prism means of the Sec. 5 source (project_f kind 2: a 10x10 collapsed
+    rule times 12-point Gauss in time) against the oracle's tensor rule at a
+    much higher order (16x16 x 24).  The two rules differ, so they agree to
+    the quadrature error of the coarser one: measured <= 8.5e-6 of max |F| on
+    the coarsest mesh, where the Gaussian is sharpest relative to a cell."""
+    from oracle import lshape as ls
+    mesh = w.lshape_mesh(4 * 2 ** level)
+    t = w.paper_times(level)
+    F = stfd.Space(mesh).project_f(t, kind=2)
+    Fo = load.prism_means(mesh, t, ls.f, 16, 24)
+    assert np.abs(F - Fo).max() <= 2e-5 * np.abs(Fo).max()
+
+
 @pytest.mark.parametrize("diagonal", ["sw-ne", "nw-se"])
 def test_dirichlet_lift_matches_oracle(diagonal):
     """Homogenisation of inhomogeneous Dirichlet data (the L-shape example of
