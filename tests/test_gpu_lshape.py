@@ -24,17 +24,17 @@ METHODS = [("fd", "fp64"), ("fd", "fp32"), ("bsc", "fp64")]
 _CACHE = {}
 
 
-def _oracle_level(level):
-    """Assembly, reference solution and errors of one level (sw-ne cells)."""
-    if level not in _CACHE:
-        case = ls.setup(level, "sw-ne")
+def _oracle_level(level, diagonal="sw-ne"):
+    """Assembly, reference solution and errors of one level."""
+    if (level, diagonal) not in _CACHE:
+        case = ls.setup(level, diagonal)
         args = (case["At"], case["Mt"], case["Mx"], case["Ax"], case["Ft"])
         if case["Ft"].size <= 40000:
             U = so.direct(*args)
         else:
             U, _ = so.refine(*args, max_iter=6)
-        _CACHE[level] = (case, U, ls.errors(case, U))
-    return _CACHE[level]
+        _CACHE[(level, diagonal)] = (case, U, ls.errors(case, U))
+    return _CACHE[(level, diagonal)]
 
 
 def _library_solve(case, method, precision):
@@ -67,6 +67,21 @@ def test_lshape_level_matches_oracle(level, method, precision):
     print(f"  rel err vs oracle {err:.2e}  rel residual {res:.2e}  iters {rep['iterations']}  "
           f"L2 {l2:.4e} H1 {h1:.4e}")
     assert err <= RTOL and res <= RTOL
+    assert abs(l2 / l2o - 1) <= 1e-8 and abs(h1 / h1o - 1) <= 1e-8
+
+
+@pytest.mark.parametrize("level", [0, 1, 2, 3])
+def test_lshape_other_diagonal_matches_oracle(level):
+    """The same example on the meshes cut along the NW-SE diagonals (the
+    level-0 triangulation is not recoverable from the text, so both cuts are
+    reported), FP32 + refinement."""
+    case, Uo, (l2o, h1o) = _oracle_level(level, "nw-se")
+    U, rep, _ = _library_solve(case, "fd", "fp32")
+    assert rep["converged"], rep
+    err = np.linalg.norm(U - Uo) / np.linalg.norm(Uo)
+    l2, h1 = ls.errors(case, U)
+    print(f"  level {level} nw-se: rel err vs oracle {err:.2e}  L2 {l2:.4e} H1 {h1:.4e}")
+    assert err <= RTOL
     assert abs(l2 / l2o - 1) <= 1e-8 and abs(h1 / h1o - 1) <= 1e-8
 
 
