@@ -310,19 +310,42 @@ bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<
 // so that a pair needs one complex inner product.
 // ---------------------------------------------------------------------------
 bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
-                std::vector<cd>& V, std::string* err) {
+                std::vector<cd>& V, std::string* err, const std::vector<cd>* v0) {
     const double eps = std::numeric_limits<double>::epsilon();
     // rotation threshold on the cosine between two columns: sqrt(n) eps, the
     // level the rounding of the column inner products allows
     const double tol = std::sqrt((double)n) * eps;
     const size_t nn = (size_t)n * n;
     std::vector<double> Ar(nn), Ai(nn), Wr(nn, 0.0), Wi(nn, 0.0), nrm(n);
-    for (int i = 0; i < n; ++i)
+    if (v0) {
+        // start from a V0 that already nearly orthogonalises the columns:
+        // columns a V0, accumulated rotations V0
+        std::vector<cd> ac(nn);
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) ac[(size_t)k * n + i] = a[(size_t)i * n + k];
+#pragma omp parallel for schedule(static)
         for (int j = 0; j < n; ++j) {
-            Ar[(size_t)j * n + i] = a[(size_t)i * n + j].real();
-            Ai[(size_t)j * n + i] = a[(size_t)i * n + j].imag();
+            std::vector<cd> col(n, 0.0);
+            for (int k = 0; k < n; ++k) {
+                const cd w = (*v0)[(size_t)k * n + j];
+                const cd* ak = &ac[(size_t)k * n];
+                for (int i = 0; i < n; ++i) col[i] += ak[i] * w;
+            }
+            for (int i = 0; i < n; ++i) {
+                Ar[(size_t)j * n + i] = col[i].real();
+                Ai[(size_t)j * n + i] = col[i].imag();
+                Wr[(size_t)j * n + i] = (*v0)[(size_t)i * n + j].real();
+                Wi[(size_t)j * n + i] = (*v0)[(size_t)i * n + j].imag();
+            }
         }
-    for (int j = 0; j < n; ++j) Wr[(size_t)j * n + j] = 1.0;
+    } else {
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                Ar[(size_t)j * n + i] = a[(size_t)i * n + j].real();
+                Ai[(size_t)j * n + i] = a[(size_t)i * n + j].imag();
+            }
+        for (int j = 0; j < n; ++j) Wr[(size_t)j * n + j] = 1.0;
+    }
     const int m = n + (n & 1);            // tournament size (pad with a dummy)
     std::vector<int> ring(m);
     for (int i = 0; i < m; ++i) ring[i] = i;
@@ -420,6 +443,81 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
         }
     }
     return true;
+}
+
+// ---------------------------------------------------------------------------
+// Right singular vectors by Householder QR with column pivoting and the
+// one-sided Jacobi SVD of R^H (Drmac and Veselic): A P = Q R and
+// R^H = U_R S V_R^H give A = (Q V_R) S (P U_R)^H, so V = P U_R.  The sweeps
+// on R^H are far fewer than on A, whose columns are far from orthogonal.
+// ---------------------------------------------------------------------------
+static bool right_vectors_qrp(int n, const std::vector<cd>& a, std::vector<cd>& V, std::string* err) {
+    const size_t nn = (size_t)n * n;
+    std::vector<cd> A(nn);                 // column-major working copy
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) A[(size_t)j * n + i] = a[(size_t)i * n + j];
+    std::vector<int> perm(n);
+    for (int j = 0; j < n; ++j) perm[j] = j;
+    std::vector<double> cn(n);
+    std::vector<cd> v(n);
+    for (int k = 0; k < n; ++k) {
+        // pivot: the remaining column of largest norm (rows k..n-1)
+#pragma omp parallel for schedule(static)
+        for (int j = k; j < n; ++j) {
+            const cd* c = &A[(size_t)j * n];
+            double t = 0.0;
+            for (int i = k; i < n; ++i) t += std::norm(c[i]);
+            cn[j] = t;
+        }
+        int p = k;
+        for (int j = k + 1; j < n; ++j)
+            if (cn[j] > cn[p]) p = j;
+        if (p != k) {
+            std::swap_ranges(A.begin() + (size_t)k * n, A.begin() + (size_t)(k + 1) * n, A.begin() + (size_t)p * n);
+            std::swap(perm[k], perm[p]);
+        }
+        // reflector H = I - tau v v^H with H x = beta e_k, beta = -e^{i arg x_k} |x|
+        cd* x = &A[(size_t)k * n];
+        const double xnorm = std::sqrt(cn[p]);
+        if (xnorm == 0.0) continue;
+        const double ax0 = std::abs(x[k]);
+        const cd ph = ax0 > 0.0 ? x[k] / ax0 : cd(1.0, 0.0);
+        const cd beta = -ph * xnorm;
+        for (int i = k; i < n; ++i) v[i] = x[i];
+        v[k] -= beta;
+        double vn2 = 0.0;
+        for (int i = k; i < n; ++i) vn2 += std::norm(v[i]);
+        if (vn2 == 0.0) continue;
+        const double tau = 2.0 / vn2;
+        x[k] = beta;
+        for (int i = k + 1; i < n; ++i) x[i] = 0.0;
+#pragma omp parallel for schedule(static)
+        for (int j = k + 1; j < n; ++j) {
+            cd* c = &A[(size_t)j * n];
+            cd t = 0.0;
+            for (int i = k; i < n; ++i) t += std::conj(v[i]) * c[i];
+            t *= tau;
+            for (int i = k; i < n; ++i) c[i] -= t * v[i];
+        }
+    }
+    // R^H, row-major: (R^H)[i][j] = conj(R[j][i]) = conj(A[i*n + j]) for j <= i
+    std::vector<cd> rh(nn, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j <= i; ++j) rh[(size_t)i * n + j] = std::conj(A[(size_t)i * n + j]);
+    std::vector<cd> UR, VR;
+    std::vector<double> sr;
+    if (!svd_jacobi(n, rh, UR, sr, VR, err)) return false;
+    V.assign(nn, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) V[(size_t)perm[i] * n + j] = UR[(size_t)i * n + j];
+    return true;
+}
+
+bool svd_jacobi_preconditioned(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
+                               std::vector<cd>& V, std::string* err) {
+    std::vector<cd> V0;
+    if (!right_vectors_qrp(n, a, V0, err)) return false;
+    return svd_jacobi(n, a, U, s, V, err, &V0);
 }
 
 // ---------------------------------------------------------------------------

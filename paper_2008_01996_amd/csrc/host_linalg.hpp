@@ -44,8 +44,17 @@ double eig_residual(int n, const double* A, const double* M, const std::vector<c
                     const std::vector<cd>& X);
 
 // One-sided Jacobi SVD of a complex n x n matrix: a = U diag(s) V^H.
-// a is row-major and destroyed; U, V row-major; s descending.
+// a is row-major; U, V row-major; s descending.  v0 (optional, row-major,
+// unitary): the sweeps start from the columns of a v0 with v0 as the
+// accumulated rotations.
 bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
-                std::vector<cd>& V, std::string* err);
+                std::vector<cd>& V, std::string* err, const std::vector<cd>* v0 = nullptr);
+
+// The same SVD, the Jacobi sweeps started from the right singular vectors of
+// a QR-with-column-pivoting preconditioned run (a few sweeps instead of tens
+// for a matrix with nearly parallel columns); U keeps the direct method's
+// column orthogonality.
+bool svd_jacobi_preconditioned(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
+                               std::vector<cd>& V, std::string* err);
 
 }  // namespace stfd

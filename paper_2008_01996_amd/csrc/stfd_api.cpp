@@ -227,7 +227,7 @@ int decompose(int n, const double* At, const double* Mt, Decomp& D) {
     for (auto& l : D.lam)
         if (!(l.real() > 0.0)) return fail(STFD_ENUMERIC, "an eigenvalue of (M_t, A_t) has Re <= 0");
     std::vector<cd> Xw = D.X;
-    if (!stfd::svd_jacobi(n, Xw, D.U, D.s, D.V, &err)) return fail(STFD_ENUMERIC, err);
+    if (!stfd::svd_jacobi_preconditioned(n, Xw, D.U, D.s, D.V, &err)) return fail(STFD_ENUMERIC, err);
     return STFD_OK;
 }
 
