@@ -80,7 +80,9 @@ static void hessenberg(int n, std::vector<double>& a, std::vector<double>& q) {
         for (int i = k + 1; i < n; ++i) vnorm2 += v[i] * v[i];
         if (vnorm2 == 0.0) continue;
         const double beta = 2.0 / vnorm2;
-        // A <- (I - beta v v^T) A   (rows k+1..n-1)
+        // A <- (I - beta v v^T) A   (rows k+1..n-1); columns, rows and rows
+        // of Q below are independent, each with its sums in the same order
+#pragma omp parallel for schedule(static)
         for (int j = k; j < n; ++j) {
             double s = 0.0;
             for (int i = k + 1; i < n; ++i) s += v[i] * a[(size_t)i * n + j];
@@ -88,6 +90,7 @@ static void hessenberg(int n, std::vector<double>& a, std::vector<double>& q) {
             for (int i = k + 1; i < n; ++i) a[(size_t)i * n + j] -= s * v[i];
         }
         // A <- A (I - beta v v^T)   (columns k+1..n-1)
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) {
             double* ai = &a[(size_t)i * n];
             double s = 0.0;
@@ -96,6 +99,7 @@ static void hessenberg(int n, std::vector<double>& a, std::vector<double>& q) {
             for (int j = k + 1; j < n; ++j) ai[j] -= s * v[j];
         }
         // Q <- Q (I - beta v v^T)
+#pragma omp parallel for schedule(static)
         for (int i = 0; i < n; ++i) {
             double* qi = &q[(size_t)i * n];
             double s = 0.0;
@@ -270,10 +274,11 @@ bool eig_real(int n, std::vector<double>& a, std::vector<cd>& vals, std::vector<
     for (auto& x : h) tnorm = std::max(tnorm, cabs1(x));
     const double smin = std::max(std::numeric_limits<double>::epsilon() * tnorm,
                                  std::numeric_limits<double>::min());
-    std::vector<cd> v(n);
     vecs.assign((size_t)n * n, 0.0);
+    // the eigenvectors are independent of each other
+#pragma omp parallel for schedule(dynamic, 4)
     for (int k = 0; k < n; ++k) {
-        std::fill(v.begin(), v.end(), cd(0.0));
+        std::vector<cd> v(n, cd(0.0));
         v[k] = 1.0;
         const cd tkk = h[(size_t)k * n + k];
         for (int i = k - 1; i >= 0; --i) {
