@@ -129,12 +129,15 @@ static inline void givens(cd x, cd y, double& c, cd& s) {
 // T = Z^H H Z accumulated into z.  Wilkinson shifts, exceptional shifts every
 // ten iterations without deflation.
 //
-// A sweep's rotations act on the column pairs (k, k+1) of H and Z.  The
-// bulge chase only reads rows k-1..k+2 of H again, so the column rotations
-// of the rows above (and all of Z, which it never reads) are kept and applied
-// after the sweep, row by row: each row then walks its rotations in order
-// over contiguous memory, and the rows run in parallel.  Every entry sees the
-// same operations in the same order as with immediate updates.
+// A sweep's rotations act on the row pairs (k, k+1) of H and on the column
+// pairs (k, k+1) of H and Z.  The bulge chase only reads columns up to ihi
+// and, of the columns k, k+1, rows k-1..k+2 again.  So the column rotations
+// of the rows above (and all of Z, which it never reads) and the row
+// rotations of the columns right of the active window (which no column
+// rotation of the sweep touches) are kept and applied after the sweep: row by
+// row, resp. in blocks of columns, each over contiguous memory and in
+// parallel.  Every entry sees the same operations in the same order as with
+// immediate updates.
 // ---------------------------------------------------------------------------
 static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::string* err) {
     const double eps = std::numeric_limits<double>::epsilon();
@@ -194,11 +197,12 @@ static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::st
             givens(x, y, cs, sn);
             rot_c[k] = cs;
             rot_s[k] = sn;
-            // rows k, k+1 from column max(k-1, l) to n-1
+            // rows k, k+1 from column max(k-1, l) to ihi; columns ihi+1..n-1
+            // follow after the sweep
             const int j0 = (k > l) ? k - 1 : l;
             cd* rk = &h[(size_t)k * n];
             cd* rk1 = &h[(size_t)(k + 1) * n];
-            for (int j = j0; j < n; ++j) {
+            for (int j = j0; j <= ihi; ++j) {
                 const cd u = rk[j], v = rk1[j];
                 rk[j] = cs * u + sn * v;
                 rk1[j] = -std::conj(sn) * u + cs * v;
@@ -213,6 +217,24 @@ static bool schur_complex(int n, std::vector<cd>& h, std::vector<cd>& z, std::st
                 const cd u = ri[k], v = ri[k + 1];
                 ri[k] = cs * u + snc * v;
                 ri[k + 1] = -sn * u + cs * v;
+            }
+        }
+        // the deferred row rotations of columns ihi+1..n-1, in blocks of 16
+        // columns (two contiguous row segments per rotation)
+        constexpr int JB = 16;
+#pragma omp parallel for schedule(static)
+        for (int jb = ihi + 1; jb < n; jb += JB) {
+            const int je = std::min(n, jb + JB);
+            for (int k = l; k < ihi; ++k) {
+                const double cs = rot_c[k];
+                const cd sn = rot_s[k], snc = std::conj(sn);
+                cd* rk = &h[(size_t)k * n];
+                cd* rk1 = &h[(size_t)(k + 1) * n];
+                for (int j = jb; j < je; ++j) {
+                    const cd u = rk[j], v = rk1[j];
+                    rk[j] = cs * u + sn * v;
+                    rk1[j] = -snc * u + cs * v;
+                }
             }
         }
         // the deferred column rotations: row i of H takes those of steps
