@@ -210,6 +210,19 @@ def test_error_paths():
         stfd.Space(bad)                              # repeated interior number
     assert e.value.code == stfd.EINVAL
     assert stfd.lib().stfd_opts_default(None) == stfd.EINVAL
+    # load projection and Dirichlet lift: bad kind, negative start time for
+    # the Sec. 5 source, null pointers
+    sp = stfd.Space(w.lshape_mesh(4))
+    L = stfd.lib()
+    tt = np.ascontiguousarray(w.paper_times(0))
+    F = np.empty((4, sp.ntri))
+    assert L.stfd_project_f(sp._h, 4, tt.ctypes.data_as(stfd.C.POINTER(stfd.C.c_double)), 3, 0, None, None, None,
+                            None, None, F.ctypes.data_as(stfd.C.POINTER(stfd.C.c_double))) == stfd.EINVAL
+    tneg = tt - 0.01
+    assert L.stfd_project_f(sp._h, 4, tneg.ctypes.data_as(stfd.C.POINTER(stfd.C.c_double)), 2, 0, None, None, None,
+                            None, None, F.ctypes.data_as(stfd.C.POINTER(stfd.C.c_double))) == stfd.EINVAL
+    assert L.stfd_dirichlet_lift(sp._h, 4, None, None, None, None) == stfd.EINVAL
+    assert L.stfd_dirichlet_lift(None, 4, None, None, None, None) == stfd.EINVAL
 
 
 def test_solve_before_factor_is_a_state_error():
