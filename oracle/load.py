@@ -37,10 +37,9 @@ def triangle_rule(n: int):
     return l1, l2, wt
 
 
-def space_means(mesh, fx, n: int = 8):
-    """Mean over every triangle of fx(x1, x2) (vectorised callable).
-
-    Returns (ntri,) array."""
+def _quadrature_points(mesh, n: int):
+    """Points (ntri, n*n) x1, x2 and weights (n*n,) of the collapsed rule
+    mapped onto every triangle of the mesh."""
     xy = np.asarray(mesh.xy, dtype=np.float64)
     tri = np.asarray(mesh.tri, dtype=np.int64)
     l1, l2, wt = triangle_rule(n)
@@ -48,32 +47,47 @@ def space_means(mesh, fx, n: int = 8):
     p1 = xy[tri[:, 1]][:, None, :]
     p2 = xy[tri[:, 2]][:, None, :]
     P = p0 + l1[None, :, None] * (p1 - p0) + l2[None, :, None] * (p2 - p0)
-    vals = fx(P[..., 0], P[..., 1])
+    return P[..., 0], P[..., 1], wt
+
+
+def space_means(mesh, fx, n: int = 8, points=None):
+    """Mean over every triangle of fx(x1, x2) (vectorised callable).
+
+    Returns (ntri,) array.  ``points``: the result of _quadrature_points for
+    this mesh and n, when the caller evaluates several functions."""
+    x1, x2, wt = _quadrature_points(mesh, n) if points is None else points
+    vals = fx(x1, x2)
     return (vals * wt[None, :]).sum(axis=1)
 
 
 def modes_cell_means(mesh, t, modes, n: int = 8):
     """F[j, l] = mean of f over omega_j x (t_{l-1}, t_l) for
     f = sum_q c_q sin(a_q pi xi1) sin(b_q pi xi2) cos(d_q pi t / T),
-    xi the bounding-box map of x onto [0,1]^2."""
+    xi the bounding-box map of x onto [0,1]^2.
+
+    Each mode is separable, so its prism mean is (space mean of the x part)
+    times (time mean of the t part); the sum over the modes is written as
+    the product Sx diag(c) St^T, Sx[j, q] the space means and St[l, q] the
+    time means."""
     t = np.asarray(t, dtype=np.float64)
     T = t[-1]
     h = np.diff(t)
     xmin, xmax, ymin, ymax = mesh.box
-    F = np.zeros((len(mesh.tri), len(h)))
-    for a, b, d, c in zip(modes.a, modes.b, modes.d, modes.c):
+    Sx = np.zeros((len(mesh.tri), len(modes.c)))
+    St = np.zeros((len(h), len(modes.c)))
+    pts = _quadrature_points(mesh, n)
+    for q, (a, b, d) in enumerate(zip(modes.a, modes.b, modes.d)):
         def fx(x1, x2, a=a, b=b):
             xi1 = (x1 - xmin) / (xmax - xmin)
             xi2 = (x2 - ymin) / (ymax - ymin)
             return np.sin(a * math.pi * xi1) * np.sin(b * math.pi * xi2)
-        sx = space_means(mesh, fx, n)
+        Sx[:, q] = space_means(mesh, fx, n, pts)
         if d == 0:
-            st = np.ones_like(h)
+            St[:, q] = 1.0
         else:
             w = d * math.pi / T
-            st = (np.sin(w * t[1:]) - np.sin(w * t[:-1])) / (w * h)
-        F += c * np.outer(sx, st)
-    return F
+            St[:, q] = (np.sin(w * t[1:]) - np.sin(w * t[:-1])) / (w * h)
+    return Sx @ (np.asarray(modes.c, dtype=np.float64)[:, None] * St.T)
 
 
 def manufactured_cell_means(mesh, t, n: int = 8):
