@@ -76,7 +76,7 @@ WORKLOADS = {
 WORKLOADS["batch96"] = dict(domain="batch", nrhs=8,
                             desc="96 problems in one batch: unit square h in {1/32, 1/64, 1/128} x uniform N_t in "
                                  "{32, 128, 512} (problem p in class p mod 9), T=1, 8 seeded smooth random RHS each")
-DEFAULT = "square128_nt256"
+DEFAULT = "lshape128_nt1024"
 
 
 def build_inputs(spec):
@@ -96,39 +96,73 @@ def build_inputs(spec):
 
 # ---------------------------------------------------------------------------
 # CPU baseline: the FP64 oracle as it stands (Algorithm FD with one sparse LU
-# per time mode, its default serial loop over the modes, FP64 refinement to
-# 1e-10), one BLAS thread, assembly excluded.  If the full solve would exceed
-# the budget, the setup and the transforms are timed in full and the spatial
-# solves on a sample of the modes, scaled to all modes and to the number of
-# FD applications of the GPU run.
+# per time mode, FP64 refinement to 1e-10), on the host cores: the spatial
+# solves of step 3 are spread over a thread pool (the time parallelism of the
+# paper; SuperLU runs outside the interpreter lock for most of its work) and
+# the dense products use that many BLAS threads; assembly excluded.  If the
+# full solve would exceed the budget, the setup and the transforms are timed
+# in full and the spatial solves on a sample of the modes (a whole number of
+# pool rounds), scaled to all modes and to the number of FD applications of
+# the GPU's FP64 form.
 # ---------------------------------------------------------------------------
+def host_cores():
+    """Threads the CPU legs use: the cores this process may run on, at most
+    16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_load(mesh, t, md, kind, M10, Ct):
+    from oracle import load
+
+    Fc = load.manufactured_cell_means(mesh, t) if kind == 1 else load.modes_cell_means(mesh, t, md)
+    return load.assemble_load(M10, Fc, Ct)
+
+
 def cpu_baseline(spec, mesh, t, modes, budget_s, napp=3):
+    from concurrent.futures import ThreadPoolExecutor
+
     from threadpoolctl import threadpool_limits
 
-    from oracle import load
     from oracle import solvers as so
     from oracle import space_matrices as sm
     from oracle import time_matrices as tm
 
+    ncores = host_cores()
     At, Mt, Ct = tm.kernel(t)
     Mx, Ax, M10 = sm.assemble(mesh)
     md, kind = modes[0]
-    Fc = load.manufactured_cell_means(mesh, t) if kind == 1 else load.modes_cell_means(mesh, t, md)
-    F = load.assemble_load(M10, Fc, Ct)
+    F = oracle_load(mesh, t, md, kind, M10, Ct)
     nt = At.shape[0]
     dofs = Mx.shape[0] * nt
-    with threadpool_limits(1):
+    where = f"{ncores} threads on {cpu_model()}"
+    with threadpool_limits(ncores), ThreadPoolExecutor(ncores) as ex:
         g = np.ones(Mx.shape[0], dtype=complex)
         t0 = time.perf_counter()
-        so._spatial_solve((Mx, Ax, 0.1 + 0.1j, g))
-        per_solve = time.perf_counter() - t0
-        if napp * nt * per_solve <= budget_s:
+        list(ex.map(so._spatial_solve, [(Mx, Ax, 0.1 + 0.1j * (k + 1), g) for k in range(ncores)]))
+        per_round = time.perf_counter() - t0           # ncores solves side by side
+        rounds = math.ceil(nt / ncores)
+        if napp * rounds * per_round <= budget_s:
             t0 = time.perf_counter()
-            U, hist = so.refine(At, Mt, Mx, Ax, F, rtol=RTOL, max_iter=10)
+            U, hist = so.refine(At, Mt, Mx, Ax, F, rtol=RTOL, max_iter=10, pool_map=ex.map)
             sec = time.perf_counter() - t0
-            return {"value": dofs / sec, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+            return {"value": dofs / sec, "unit": "DOF/s", "cores": ncores, "kind": "oracle",
                     "sample": f"full solve of RHS 0 ({len(hist)} FD applications, rel. residual {hist[-1]:.1e}), "
-                              f"{sec:.1f} s, assembly excluded",
+                              f"{sec:.1f} s, {where}, assembly excluded",
                     "seconds": sec}, U
         t0 = time.perf_counter()
         dec = so.decompose(At, Mt)
@@ -137,9 +171,10 @@ def cpu_baseline(spec, mesh, t, modes, budget_s, napp=3):
         W = np.linalg.solve(At, dec.Ut.conj())
         G = ((F @ W) / dec.sig) @ dec.Vt.T
         t_fwd = time.perf_counter() - t0
-        nsamp = int(min(nt, max(2, 0.7 * budget_s / max(per_solve, 1e-3))))
+        nround = int(min(rounds, max(1, 0.6 * budget_s / max(per_round, 1e-3))))
+        nsamp = min(nt, nround * ncores)
         t0 = time.perf_counter()
-        Z = np.stack([so._spatial_solve((Mx, Ax, dec.lam[k], G[:, k])) for k in range(nsamp)], axis=1)
+        Z = np.stack(list(ex.map(so._spatial_solve, [(Mx, Ax, dec.lam[k], G[:, k]) for k in range(nsamp)])), axis=1)
         t_solves = (time.perf_counter() - t0) * nt / nsamp
         Zf = np.zeros((Mx.shape[0], nt), dtype=complex)
         Zf[:, :nsamp] = Z
@@ -150,51 +185,74 @@ def cpu_baseline(spec, mesh, t, modes, budget_s, napp=3):
         so.residual(At, Mt, Mx, Ax, F, np.zeros_like(F))
         t_res = time.perf_counter() - t0
     sec = t_dec + napp * (t_fwd + t_solves + t_back + t_res)
-    return {"value": dofs / sec, "unit": "DOF/s", "cores": 1, "kind": "oracle",
+    return {"value": dofs / sec, "unit": "DOF/s", "cores": ncores, "kind": "oracle",
             "sample": f"RHS 0; eigendecomposition/SVD, transforms and residual timed in full, {nsamp} of {nt} "
-                      f"spatial sparse-LU solves timed and scaled to all {nt} modes, {napp} FD applications "
-                      f"(as the FP64 form on the GPU); estimated {sec:.1f} s; assembly excluded",
+                      f"spatial sparse-LU solves timed ({ncores} at a time) and scaled to all {nt} modes, {napp} FD "
+                      f"applications (as the FP64 form on the GPU); estimated {sec:.1f} s; {where}; assembly "
+                      f"excluded",
             "seconds": sec}, None
 
 
-def oracle_check(mesh, t, modes, Ugpu, U_oracle):
-    """Relative residual of the GPU solution under the oracle's own K_h and
-    load (FP64, host), and its relative error vs the oracle's solution when
-    that was computed."""
-    from oracle import load
+def oracle_check(mesh, t, modes, Us, U_oracle):
+    """Per right-hand side, the relative residual of each GPU solution in Us
+    ({form: (nrhs, N_t, M_x) array}) under the oracle's own K_h and load
+    (FP64, host; the loads are built in a thread pool), the maximum over the
+    right-hand sides; and the relative error of RHS 0 vs the oracle's
+    solution where that was computed."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from threadpoolctl import threadpool_limits
+
     from oracle import solvers as so
     from oracle import space_matrices as sm
     from oracle import time_matrices as tm
 
     At, Mt, Ct = tm.kernel(t)
     Mx, Ax, M10 = sm.assemble(mesh)
-    out = {"rel_residual_oracle_Kh": [], "rel_error_vs_oracle": None}
-    for q, (md, kind) in enumerate(modes):
-        Fc = load.manufactured_cell_means(mesh, t) if kind == 1 else load.modes_cell_means(mesh, t, md)
-        F = load.assemble_load(M10, Fc, Ct)
-        out["rel_residual_oracle_Kh"].append(so.rel_residual(At, Mt, Mx, Ax, F, Ugpu[q].T))
-    out["rel_residual_oracle_Kh"] = max(out["rel_residual_oracle_Kh"])
-    if U_oracle is not None:
-        Ug = Ugpu[0].T
-        out["rel_error_vs_oracle"] = float(np.linalg.norm(Ug - U_oracle) / np.linalg.norm(U_oracle))
+    nw = min(host_cores(), 8, len(modes))
+
+    def one(q):
+        md, kind = modes[q]
+        F = oracle_load(mesh, t, md, kind, M10, Ct)
+        return [so.rel_residual(At, Mt, Mx, Ax, F, U[q].T) for U in Us.values()]
+
+    with threadpool_limits(max(1, host_cores() // nw)), ThreadPoolExecutor(nw) as ex:
+        res = np.array(list(ex.map(one, range(len(modes)))))
+    out = {}
+    for j, form in enumerate(Us):
+        o = {"rel_residual_oracle_Kh": float(res[:, j].max()), "rhs_checked": len(modes),
+             "rel_error_vs_oracle": None}
+        if U_oracle is not None:
+            Ug = Us[form][0].T
+            o["rel_error_vs_oracle"] = float(np.linalg.norm(Ug - U_oracle) / np.linalg.norm(U_oracle))
+        out[form] = o
     return out
 
 
-def factor_flops(Mx, b, nsys):
+def band_envelope(sp):
+    """m_c = (last row of the band of column c) - c for the spatial matrix:
+    the envelope of M_x + lambda A_x, which the pivot-free LDL^T keeps (the
+    fill of column c stays above the last row any earlier column reaches)."""
+    rp, cl, _, (n, _) = sp.csr(0)
+    last = np.maximum.reduceat(cl, rp[:-1])          # every row holds its diagonal
+    reach = np.maximum.accumulate(last)
+    return (reach - np.arange(n)).astype(np.float64)
+
+
+def factor_flops(env, nsys):
     """Band LDL^T flops: column c updates the m(m+1)/2 lower triangle below
-    it with complex multiply-adds (8 flops each), m = min(b, Mx-1-c)."""
-    c = np.arange(Mx)
-    m = np.minimum(b, Mx - 1 - c).astype(np.float64)
-    return float(nsys * (4.0 * m * (m + 1)).sum())
+    it with complex multiply-adds (8 flops each), m = m_c the envelope."""
+    return float(nsys * (4.0 * env * (env + 1)).sum())
 
 
-def stage_work(stage, Mx, Nt, b, nsys, nrhs, es):
+def stage_work(stage, Mx, Nt, env, nsys, nrhs, es):
     """(kind, algorithmic units per launch): flops for MFMA stages, bytes for
-    the HBM-bound sweeps."""
+    the HBM-bound sweeps (every factor entry inside the envelope read once,
+    the right-hand side read and the result written; es = bytes per real)."""
     if stage == "band_ldl":
-        return "mfma", factor_flops(Mx, b, nsys)
+        return "mfma", factor_flops(env, nsys)
     if stage in ("sweep_fwd", "sweep_bwd"):
-        return "hbm", nsys * Mx * (b + 1) * 2 * es + 2 * nsys * Mx * 2 * nrhs * es
+        return "hbm", nsys * float((env + 1).sum()) * 2 * es + 2 * nsys * Mx * 2 * nrhs * es
     if stage == "fwd1":
         return "mfma", 2.0 * Mx * (2 * Nt) * Nt * nrhs
     if stage == "fwd2":
@@ -281,7 +339,7 @@ def run_gpu(loads, t, precision, steps, warmup, method="fd"):
     prob.profile(False)
     Uh = U.cpu().numpy()
     return {"sec": sec, "setup_s": setup_s, "reps": reps, "prof": prof, "U": Uh,
-            "setup": prob.setup_report, "Mx": sp.Mx, "b": sp.half_band}
+            "setup": prob.setup_report, "Mx": sp.Mx, "b": sp.half_band, "env": band_envelope(sp)}
 
 
 def cpu_bsc(mesh, t, modes, budget_s):
@@ -341,13 +399,15 @@ def run_batch(steps, warmup, precision):
 
     from paper_2008_01996_amd import stfd
 
-    spaces, tmats, probs, Fd, Ud = {}, {}, [], [], []
+    spaces, envs, tmats, probs, Fd, Ud, penv = {}, {}, {}, [], [], [], []
     dofs = 0
     t0 = time.perf_counter()
     for pidx in range(96):
         nc, nt = w.batch_problem_class(pidx)
         if nc not in spaces:
             spaces[nc] = stfd.Space(w.square_mesh(nc))
+            envs[nc] = band_envelope(spaces[nc])
+        penv.append(envs[nc])
         if nt not in tmats:
             tmats[nt] = (w.uniform_times(nt),) + tuple(stfd.assemble_time(w.uniform_times(nt)))
         sp = spaces[nc]
@@ -377,14 +437,14 @@ def run_batch(steps, warmup, precision):
     sec = (time.perf_counter() - t0) / steps
     prof = {}
     work = {}
-    for p, F in zip(probs, Fd):
+    for p, F, env in zip(probs, Fd, penv):
         pr = p.profile_read()
         nsys = p.setup_report["n_sys"]
         for k, (ms, n) in pr.items():
             tot = prof.setdefault(k, [0.0, 0])
             tot[0] += ms
             tot[1] += n
-            kind, units = stage_work(k, p.Mx, p.Nt, p.setup_report["half_band"], nsys, F.shape[0], 4)
+            kind, units = stage_work(k, p.Mx, p.Nt, env, nsys, F.shape[0], 4)
             if kind:
                 work[k] = work.get(k, 0.0) + (units or 0.0) * n
         p.profile(False)
@@ -408,7 +468,7 @@ def main_batch(args):
     prof = m["prof"]
     dom = max(prof, key=lambda k: prof[k][0])
     ms_tot, launches = prof[dom]
-    kind = stage_work(dom, 1, 1, 1, 1, 1, 4)[0]
+    kind = stage_work(dom, 1, 1, np.zeros(1), 1, 1, 4)[0]
     achieved = m["work"].get(dom, 0.0) / (ms_tot * 1e-3)
     if kind == "hbm":
         roof = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
@@ -498,7 +558,7 @@ def main():
         bms, bn = bprof[bdom]
         bavg = bms / max(bn, 1)
         # a sequential sweep runs one system: its units are one system's bytes
-        bkind, bunits = stage_work(bdom, Mx0, Nt0, rb["b"], 1 if bdom.startswith("sweep") else Nt0,
+        bkind, bunits = stage_work(bdom, Mx0, Nt0, rb["env"], 1 if bdom.startswith("sweep") else Nt0,
                                    spec["nrhs"], 8)
         if bkind == "hbm":
             broof = {"bound": "hbm", "achieved": bunits / (bavg * 1e-3) / 1e9, "peak": PEAK["hbm_GBs"],
@@ -529,7 +589,8 @@ def main():
     ms_tot, launches = prof[dom]
     avg_ms = ms_tot / max(launches, 1)
     es = 4  # bytes per real in the FP32 form's band factor and sweeps
-    kind, units = stage_work(dom, Mx, Nt, b, nsys, nrhs, es)
+    env = main_r["env"]
+    kind, units = stage_work(dom, Mx, Nt, env, nsys, nrhs, es)
     if kind == "hbm":
         achieved = units / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK["hbm_GBs"], "unit": "GB/s"}
@@ -551,15 +612,16 @@ def main():
     sweeps = {}
     for sname in ("sweep_fwd", "sweep_bwd"):
         ms, n = prof[sname]
-        _, byts = stage_work(sname, Mx, Nt, b, nsys, nrhs, es)
+        _, byts = stage_work(sname, Mx, Nt, env, nsys, nrhs, es)
         gbs = byts / (ms / max(n, 1) * 1e-3) / 1e9
         sweeps[sname] = {"avg_launch_ms": ms / max(n, 1), "bytes_per_launch": byts, "achieved_GBs": gbs,
                          "frac_hbm_peak": gbs / PEAK["hbm_GBs"]}
 
     chk = {}
     if not args.no_cpu_baseline:
-        for prec in ("fp32", "fp64"):
-            chk[prec] = oracle_check(mesh, t, modes, res[prec]["U"], U_oracle)
+        print("# oracle check: residual of every right-hand side under the oracle's K_h and load", file=sys.stderr,
+              flush=True)
+        chk = oracle_check(mesh, t, modes, {prec: res[prec]["U"] for prec in ("fp32", "fp64")}, U_oracle)
 
     v32 = dofs / main_r["sec"]
     v64 = dofs / res["fp64"]["sec"]

@@ -327,22 +327,31 @@ extern "C" int stfd_assemble_load(const stfd_space* s, int Nt, const double* Ct,
                 acc += s->val10[e] * F[(size_t)l * nt + s->col10[e]];
             G[(size_t)l * Mx + i] = acc;
         }
-    // Ft = G Ct^T in blocks of rows (a block of G stays in cache over k)
-    constexpr int RB = 128;
+    // Ft = G Ct^T in blocks of rows (a block of G stays in cache over k),
+    // KB columns of Ft at a time (each G entry loaded once for KB products)
+    constexpr int RB = 128, KB = 8;
     const int nblk = (Mx + RB - 1) / RB;
 #pragma omp parallel for schedule(static)
     for (int bi = 0; bi < nblk; ++bi) {
-        const int i0 = bi * RB, i1 = std::min(Mx, i0 + RB);
-        double acc[RB];
-        for (int k = 0; k < Nt; ++k) {
-            for (int i = 0; i < i1 - i0; ++i) acc[i] = 0.0;
+        const int i0 = bi * RB, nr = std::min(Mx, i0 + RB) - i0;
+        double acc[KB][RB];
+        for (int k0 = 0; k0 < Nt; k0 += KB) {
+            const int nk = std::min(KB, Nt - k0);
+            for (int j = 0; j < KB; ++j)
+                for (int i = 0; i < RB; ++i) acc[j][i] = 0.0;
             for (int l = 0; l < Nt; ++l) {
-                const double ckl = Ct[(size_t)k * Nt + l];
+                double c[KB];
+                for (int j = 0; j < KB; ++j) c[j] = j < nk ? Ct[(size_t)(k0 + j) * Nt + l] : 0.0;
                 const double* g = &G[(size_t)l * Mx + i0];
-                for (int i = 0; i < i1 - i0; ++i) acc[i] += ckl * g[i];
+                for (int i = 0; i < nr; ++i) {
+                    const double gi = g[i];
+                    for (int j = 0; j < KB; ++j) acc[j][i] += c[j] * gi;
+                }
             }
-            double* out = Ft + (size_t)k * Mx + i0;
-            for (int i = 0; i < i1 - i0; ++i) out[i] = acc[i];
+            for (int j = 0; j < nk; ++j) {
+                double* out = Ft + (size_t)(k0 + j) * Mx + i0;
+                for (int i = 0; i < nr; ++i) out[i] = acc[j][i];
+            }
         }
     }
     return STFD_OK;

@@ -248,6 +248,24 @@ class Space:
         return out.T
 
 
+def _check_tensor(name, x, dtype, shape, device):
+    """Raise ValueError unless x is a contiguous torch tensor of that dtype and
+    shape on that device: the library reads and writes exactly that many
+    elements at the pointer, so a mismatch must stop here, on the host."""
+    import torch
+
+    if not isinstance(x, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(x).__name__}")
+    if x.dtype != dtype:
+        raise ValueError(f"{name}: dtype {x.dtype}, expected {dtype}")
+    if x.device != device:
+        raise ValueError(f"{name}: on {x.device}, expected {device}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name}: not contiguous")
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"{name}: shape {tuple(x.shape)}, expected {tuple(shape)}")
+
+
 def _stream_ptr(stream):
     if stream is None:
         import torch
@@ -278,6 +296,9 @@ class Problem:
         o.method = {"fd": METHOD_FD, "bsc": METHOD_BSC}[method]
         self.precision = precision
         self.method = method
+        import torch
+
+        self.device = torch.device("cuda", torch.cuda.current_device())
         self._h = C.c_void_p()
         _check(lib().stfd_fd_setup(space._h, self.Nt, _dp(At), _dp(Mt), C.byref(o),
                                    C.c_void_p(_stream_ptr(stream)), C.byref(self._h)))
@@ -294,29 +315,55 @@ class Problem:
     def factor(self, stream=None):
         _check(lib().stfd_fd_factor(self._h, C.c_void_p(_stream_ptr(stream))))
 
-    def solve(self, F, U, stream=None, check=True):
-        """F, U: torch float64 CUDA tensors of shape (nrhs, N_t, M_x) (the
-        [rhs][k][i] layout).  Returns the solve report as a dict."""
-        assert F.dtype == U.dtype and F.is_contiguous() and U.is_contiguous()
-        assert F.shape == U.shape and F.shape[1:] == (self.Nt, self.Mx)
+    def _rhs_shape(self, X, name):
+        import torch
+
+        if not isinstance(X, torch.Tensor) or X.dim() != 3 or X.shape[0] < 1:
+            raise ValueError(f"{name}: expected a (nrhs, N_t, M_x) tensor")
+        return (X.shape[0], self.Nt, self.Mx)
+
+    def _solve(self, fn, F, U, stream, check):
+        import torch
+
+        shape = self._rhs_shape(F, "F")
+        _check_tensor("F", F, torch.float64, shape, self.device)
+        _check_tensor("U", U, torch.float64, shape, self.device)
         rep = SolveReport()
-        rc = lib().stfd_fd_solve(self._h, F.shape[0], C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
-                                 C.byref(rep), C.c_void_p(_stream_ptr(stream)))
+        rc = fn(self._h, F.shape[0], C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()), C.byref(rep),
+                C.c_void_p(_stream_ptr(stream)))
         out = rep.as_dict()
         out["status"] = rc
         if check:
             _check(rc)
         return out
 
+    def solve(self, F, U, stream=None, check=True):
+        """F, U: torch float64 CUDA tensors of shape (nrhs, N_t, M_x) (the
+        [rhs][k][i] layout).  Returns the solve report as a dict."""
+        return self._solve(lib().stfd_fd_solve, F, U, stream, check)
+
     def apply(self, X, U, stream=None):
         """One FD application without refinement: U = FD(X) (device tensors
         (nrhs, N_t, M_x) float64)."""
+        import torch
+
+        shape = self._rhs_shape(X, "X")
+        _check_tensor("X", X, torch.float64, shape, self.device)
+        _check_tensor("U", U, torch.float64, shape, self.device)
         _check(lib().stfd_fd_apply(self._h, X.shape[0], C.c_void_p(X.data_ptr()), C.c_void_p(U.data_ptr()),
                                    C.c_void_p(_stream_ptr(stream))))
 
     def spatial_solve(self, G, Z, stream=None):
         """Step 3 alone on device tensors of shape (nrhs, 2 n_sys, M_x) in the
         working precision (float32 for fp32, float64 for fp64)."""
+        import torch
+
+        dt = torch.float32 if self.precision == "fp32" else torch.float64
+        if not isinstance(G, torch.Tensor) or G.dim() != 3 or G.shape[0] < 1:
+            raise ValueError("G: expected a (nrhs, 2 n_sys, M_x) tensor")
+        shape = (G.shape[0], 2 * self.setup_report["n_sys"], self.Mx)
+        _check_tensor("G", G, dt, shape, self.device)
+        _check_tensor("Z", Z, dt, shape, self.device)
         _check(lib().stfd_spatial_solve(self._h, G.shape[0], C.c_void_p(G.data_ptr()), C.c_void_p(Z.data_ptr()),
                                         C.c_void_p(_stream_ptr(stream))))
 
@@ -339,6 +386,11 @@ class Problem:
 
     def kh_residual(self, F, U, R, stream=None):
         """R = F - K_h U on the device; returns (||R||^2, ||F||^2) per RHS."""
+        import torch
+
+        shape = self._rhs_shape(F, "F")
+        for name, x in (("F", F), ("U", U), ("R", R)):
+            _check_tensor(name, x, torch.float64, shape, self.device)
         n = F.shape[0]
         norms = np.empty(2 * n)
         _check(lib().stfd_kh_residual(self._h, n, C.c_void_p(F.data_ptr()), C.c_void_p(U.data_ptr()),
@@ -369,11 +421,15 @@ class Batch:
     def solve(self, Fs, Us, stream=None, check=True):
         """Fs, Us: lists of torch float64 CUDA tensors (nrhs_i, N_t_i, M_x_i).
         Returns (status, list of per-problem report dicts)."""
+        import torch
+
         n = len(self.problems)
-        assert len(Fs) == n and len(Us) == n
-        for p, F, U in zip(self.problems, Fs, Us):
-            assert F.is_contiguous() and U.is_contiguous() and F.shape == U.shape
-            assert F.shape[1:] == (p.Nt, p.Mx)
+        if len(Fs) != n or len(Us) != n:
+            raise ValueError(f"batch solve: {n} problems, {len(Fs)} loads and {len(Us)} solutions")
+        for i, (p, F, U) in enumerate(zip(self.problems, Fs, Us)):
+            shape = p._rhs_shape(F, f"Fs[{i}]")
+            _check_tensor(f"Fs[{i}]", F, torch.float64, shape, p.device)
+            _check_tensor(f"Us[{i}]", U, torch.float64, shape, p.device)
         nr = (C.c_int * n)(*[F.shape[0] for F in Fs])
         fp = (C.c_void_p * n)(*[F.data_ptr() for F in Fs])
         up = (C.c_void_p * n)(*[U.data_ptr() for U in Us])

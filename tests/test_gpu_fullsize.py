@@ -1,0 +1,172 @@
+"""GPU parity at the full sizes of the benchmark workloads, in the launch
+configuration bench.py times (the same kernel variants: right-hand-side
+counts, band widths, FP32 form with the default transform mask).
+
+The oracle cannot solve these problems in test time (about a thousand
+sparse LU factorizations of 5e4 unknowns for the L-shape), so parity is
+checked through properties that hold at any size:
+  * the relative residual of every right-hand side under the oracle's own
+    K_h (Kronecker identity, Sec. 3.1) and load (Sec. 2), with the GPU fed
+    the oracle's time matrices and load;
+  * step 3 alone (band LDL^T and both sweeps, Alg. FD step 3) on three
+    systems (smallest Re lambda, largest |lambda|, a real lambda) against the
+    oracle's sparse LU solves, one by one: forward error within
+    4 (b + 1) u kappa_2(S) and normwise backward error within 4 (b + 1) u
+    (banded LU without pivoting, Higham Thm. 9.3, with |L||D||L^T| of the
+    size of |S| for these complex symmetric systems).
+
+Workloads: the L-shape (-1,1)^2 minus [0,1]x[-1,0] at h = 1/128 (M_x =
+48641, half-bandwidth 256) with the graded time mesh t_i = (i/N_t)^2, N_t =
+1024, 16 right-hand sides; the unit square at h = 1/256 (M_x = 65025) with
+uniform N_t = 512 and 4 right-hand sides.  The L-shape band factor holds
+6.4e9 complex entries per form, so its offsets pass 2^31.
+"""
+import gc
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spl
+
+import workloads as w
+from oracle import load
+from oracle import solvers as so
+from oracle import space_matrices as sm
+from oracle import time_matrices as tm
+
+torch = pytest.importorskip("torch")
+from paper_2008_01996_amd import stfd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+SOLVE_RTOL = 5e-11
+UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
+NTHREADS = 8
+
+
+def _oracle_problem(mesh, t, seeds):
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, M10 = sm.assemble(mesh)
+
+    def one(sd):
+        return load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(sd)), Ct)
+
+    with ThreadPoolExecutor(NTHREADS) as ex:
+        Fs = list(ex.map(one, seeds))
+    return At, Mt, Mx, Ax, Fs
+
+
+_CACHE = {}
+
+
+def _case(name):
+    if name not in _CACHE:
+        _CACHE.clear()
+        gc.collect()
+        if name == "lshape128_nt1024":
+            mesh, t = w.lshape_mesh(256), w.graded_times(1024, 1.0)
+            seeds = w.rhs_seeds("lshape_nt1024", 16)
+        else:
+            mesh, t = w.square_mesh(256), w.uniform_times(512, 1.0)
+            seeds = w.rhs_seeds("square256_nt512", 4)
+        print(f"  building the oracle's matrices and {len(seeds)} loads for {name}", flush=True)
+        _CACHE[name] = (mesh, t) + _oracle_problem(mesh, t, seeds)
+    return _CACHE[name]
+
+
+def _free_device():
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", ["lshape128_nt1024", "square256_nt512"])
+def test_full_size_residual_under_oracle_kh(name, precision):
+    mesh, t, At, Mt, Mx, Ax, Fs = _case(name)
+    print(f"  {name} {precision}: M_x = {Mx.shape[0]}, N_t = {At.shape[0]}, {len(Fs)} RHS", flush=True)
+    sp = stfd.Space(mesh)
+    prob = stfd.Problem(sp, At, Mt, precision=precision, rtol=SOLVE_RTOL, max_refine=30)
+    if name == "lshape128_nt1024":
+        assert sp.half_band == 256 and prob.setup_report["n_sys"] == 513
+    prob.factor()
+    F = torch.from_numpy(np.ascontiguousarray(np.stack([Fq.T for Fq in Fs]))).to("cuda:0")
+    U = torch.empty_like(F)
+    rep = prob.solve(F, U)
+    torch.cuda.synchronize()
+    Uh = U.cpu().numpy()
+    del prob, F, U
+    _free_device()
+    assert rep["converged"], rep
+    with ThreadPoolExecutor(NTHREADS) as ex:
+        res = list(ex.map(lambda q: so.rel_residual(At, Mt, Mx, Ax, Fs[q], Uh[q].T), range(len(Fs))))
+    print(f"  applications {rep['iterations']}, residual history {rep['rel_residual']}", flush=True)
+    print(f"  residual under the oracle's K_h per RHS: max {max(res):.2e}, min {min(res):.2e}", flush=True)
+    assert max(res) <= RTOL
+
+
+def _cond2_estimate(S, lu):
+    """kappa_2(S) estimated as ||S||_1 / sigma_min: ||S||_2 <= ||S||_1 for
+    the complex symmetric S, and sigma_min from inverse iteration on S^H S
+    with the LU factors (its Rayleigh quotient converges from above to
+    sigma_min, the lowest singular values of these matrices being well
+    apart)."""
+    norm1 = float(abs(S).sum(axis=0).max())
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(S.shape[0]) + 1j * rng.standard_normal(S.shape[0])
+    x /= np.linalg.norm(x)
+    mu = 0.0
+    for _ in range(40):
+        y = lu.solve(lu.solve(x, trans="H"))       # (S^H S)^-1 x = S^-1 S^-H x
+        mu = float(np.real(np.vdot(x, y)))
+        x = y / np.linalg.norm(y)
+    return norm1 * np.sqrt(mu)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_full_size_step3_three_systems_vs_oracle_lu(precision):
+    """L-shape, M_x = 48641, 513 systems, 16 right-hand sides: every system
+    solved on the GPU; three of them checked against the oracle's sparse LU."""
+    mesh, t = w.lshape_mesh(256), w.graded_times(1024, 1.0)
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, _ = sm.assemble(mesh)
+    sp = stfd.Space(mesh)
+    prob = stfd.Problem(sp, At, Mt, precision=precision)
+    prob.factor()
+    lam = prob.system_lambdas()
+    n, m, nrhs = len(lam), Mx.shape[0], 16
+    assert n == 513 and prob.setup_report["n_real"] >= 1
+    rng = np.random.default_rng(8500)
+    G = rng.standard_normal((nrhs, 2 * n, m))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Gd = torch.from_numpy(G).to("cuda:0", dt)
+    G = Gd.double().cpu().numpy()                  # the values the GPU solved with
+    Z = torch.empty_like(Gd)
+    prob.spatial_solve(Gd, Z)
+    torch.cuda.synchronize()
+    Zh = Z.double().cpu().numpy()
+    b = prob.setup_report["half_band"]
+    del prob, Gd, Z
+    _free_device()
+    real = [k for k in range(n) if lam[k].imag == 0.0]
+    picks = {"min Re": int(np.argmin(lam.real)), "max |lambda|": int(np.argmax(np.abs(lam))), "real": real[0]}
+    u = UNIT_ROUNDOFF[precision]
+    for what, k in picks.items():
+        S = (Mx + lam[k] * Ax).tocsc().astype(np.complex128)
+        lu = spl.splu(S)
+        kappa = _cond2_estimate(S, lu)
+        fwd_tol = 4 * (b + 1) * u * kappa
+        bwd_tol = 4 * (b + 1) * u
+        normS = float(abs(S).sum(axis=0).max())
+        worst_f = worst_b = 0.0
+        for q in range(nrhs):
+            g = G[q, k] + 1j * G[q, n + k]
+            z = Zh[q, k] + 1j * Zh[q, n + k]
+            zo = lu.solve(g)
+            worst_f = max(worst_f, np.linalg.norm(z - zo) / np.linalg.norm(zo))
+            worst_b = max(worst_b, np.linalg.norm(g - S @ z) / (normS * np.linalg.norm(z) + np.linalg.norm(g)))
+        print(f"  {what}: lambda {lam[k]:.3e}, kappa_2 ~ {kappa:.2e}: forward error {worst_f:.2e} "
+              f"(bound {fwd_tol:.2e}), backward error {worst_b:.2e} (bound {bwd_tol:.2e})", flush=True)
+        assert worst_f <= fwd_tol
+        assert worst_b <= bwd_tol

@@ -231,3 +231,40 @@ def test_solve_before_factor_is_a_state_error():
     rep = stfd.SolveReport()
     rc = lib.stfd_fd_solve(None, 1, None, None, ctypes.byref(rep), None)
     assert rc == stfd.EINVAL
+
+
+def test_binding_rejects_bad_tensors_before_the_library():
+    """The binding checks dtype, device, contiguity and exact shape of every
+    device buffer before the call: a wrong buffer must raise on the host, not
+    become an out-of-bounds access on the GPU.  A problem stub (no handle)
+    stands in for a set-up problem; its device is the CPU so that the shape
+    checks are reached without a GPU."""
+    torch = pytest.importorskip("torch")
+    p = stfd.Problem.__new__(stfd.Problem)
+    p.Nt, p.Mx, p.precision, p.setup_report = 4, 9, "fp64", {"n_sys": 2}
+    p._h = ctypes.c_void_p()
+    p.device = torch.device("cpu")
+    z = lambda *s, dt=torch.float64: torch.zeros(s, dtype=dt)
+    bad_pairs = [
+        (z(2, 4, 9, dt=torch.float32), z(2, 4, 9)),        # dtype of F
+        (z(2, 4, 9), z(2, 4, 9, dt=torch.float32)),        # dtype of U
+        (z(2, 5, 9), z(2, 5, 9)),                          # N_t
+        (z(2, 4, 9), z(1, 4, 9)),                          # U shorter than F
+        (z(2, 4, 9), z(2, 9, 4).transpose(1, 2)),          # not contiguous
+        (z(4, 9), z(4, 9)),                                # rank
+    ]
+    for F, U in bad_pairs:
+        for fn in (p.solve, p.apply):
+            with pytest.raises(ValueError):
+                fn(F, U)
+        with pytest.raises(ValueError):
+            p.kh_residual(F, U, z(*F.shape))
+    with pytest.raises(ValueError):
+        p.kh_residual(z(2, 4, 9), z(2, 4, 9), z(2, 4, 8))  # R of the wrong size
+    with pytest.raises(ValueError):
+        p.spatial_solve(z(1, 4, 9, dt=torch.float32), z(1, 4, 9, dt=torch.float32))  # fp64 problem
+    with pytest.raises(ValueError):
+        p.spatial_solve(z(1, 3, 9), z(1, 3, 9))            # 2 n_sys rows
+    p.device = torch.device("cuda", 0)
+    with pytest.raises(ValueError):
+        p.solve(z(2, 4, 9), z(2, 4, 9))                    # host tensors for a device problem
