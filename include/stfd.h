@@ -79,6 +79,24 @@ typedef struct {
     double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
     int max_refine;       /* maximum number of refinement corrections (default 30) */
     int method;           /* STFD_METHOD_FD (default) or STFD_METHOD_BSC */
+    int inner_refine;     /* FD only, 0 or 1: steps of refinement of the spatial
+                             solves inside each application (the residual
+                             g_k - (M_x + lambda_k A_x) z_k formed in FP64 from
+                             the stored g_k and z_k, solved with the same band
+                             factors, the correction added to z_k).  Default 0. */
+    int graph;            /* FD only: 1 = the refinement rounds of stfd_fd_solve and
+                             stfd_batch_solve run as captured HIP graphs
+                             (apply, residual and a device-side convergence check;
+                             rounds after convergence do no work), with one host
+                             synchronisation per solve as a rule; 0 = launched one
+                             by one, one host synchronisation per round.  The
+                             graph is built on the first solve with a given
+                             (F, U, nrhs) and reused.  Per-stage timing
+                             (stfd_profile) runs the rounds one by one.  Default 1. */
+    int nrhs_max;         /* > 0: stfd_fd_setup allocates the band factors and the
+                             work buffers for this many right-hand sides, so that
+                             factor and solve allocate nothing (up to nrhs_max
+                             right-hand sides).  Default 0: allocated on first use. */
 } stfd_opts;
 
 typedef struct {
@@ -241,6 +259,54 @@ int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, const doubl
 int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* rep);
 
 /* ---------------------------------------------------------------------------
+ * Kernel variants of a problem (what the autotuner of the Python package,
+ * paper_2008_01996_amd/autotune.py, chooses per shape and writes to its
+ * cache; the binding applies a cached choice right after setup).  None of
+ * them changes the method, only the kernels that carry out its steps:
+ *   sweep_tile_min_rhs  the substitution sweeps of step 3 (Alg. FD) run the
+ *                       matrix-core tile kernels, up to 16 right-hand sides
+ *                       per workgroup, from this many right-hand sides on;
+ *                       0 = never (the lane-chain sweeps for every count).
+ *                       Needs a padded half-bandwidth <= 256.  Default 8
+ *                       (Algorithm FD; Algorithm BSc always takes the
+ *                       lane-chain sweeps, one system at a time).
+ *   gemm_tile_m_fp32    rows of the workgroup tile of the transform GEMMs
+ *   gemm_tile_m_fp64    (Alg. FD steps 2 and 4) on FP32 and on FP64 matrix
+ *                       cores: 64 or 128 (the residual GEMM keeps 64).
+ *   gemm_n_fast         1: consecutive workgroups of a GEMM walk along its
+ *                       columns (those sharing a panel of the space-time
+ *                       block run side by side); 0: along its rows.
+ *   factor_kernel       the band LDL^T (step 3 of Alg. FD, first half):
+ *                       0 = automatic (register window for FP32 with padded
+ *                       half-bandwidth 128, LDS window where it fits, else
+ *                       the panel kernel), 1 = trailing tiles streamed with
+ *                       the panel factored in LDS, 2 = panel factored in
+ *                       registers with the trailing tiles streamed and the
+ *                       next panel handed over on chip.
+ *   factor_pack_real    1 (default): the panel kernel (2, and the automatic
+ *                       choice where it takes that kernel) factors the real
+ *                       systems of Alg. FD (real lambda, ordered last) two
+ *                       to a workgroup in real arithmetic, e.g. 2 p + 2
+ *                       systems on 2 p + 1 workgroups; 0: one complex
+ *                       workgroup each.  The factors are the same bit for
+ *                       bit.  The other kernels ignore it.
+ * stfd_set_tuning takes effect from the next stfd_fd_factor (the tile
+ * sweeps need the inverses of the diagonal blocks, formed by the factor).
+ * Errors: STFD_EINVAL (null pointers, a value out of range).  Host only.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int sweep_tile_min_rhs;
+    int gemm_tile_m_fp32;
+    int gemm_tile_m_fp64;
+    int gemm_n_fast;
+    int factor_kernel;
+    int factor_pack_real;
+} stfd_tuning;
+
+int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t);
+int stfd_set_tuning(stfd_problem* p, const stfd_tuning* t);
+
+/* ---------------------------------------------------------------------------
  * stfd_fd_factor: step 3, first half.  For every system k (one per
  * conjugate pair, Im(lambda_k) > 0, and one per real eigenvalue) factors
  *     M_x + lambda_k A_x = L_k D_k L_k^T
@@ -300,13 +366,14 @@ int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, const doubl
  * Stages: STFD_ST_BAND_INIT, STFD_ST_BAND_LDL (factor), STFD_ST_FWD1,
  * STFD_ST_FWD2 (forward transforms), STFD_ST_SWEEP_FWD, STFD_ST_SWEEP_BWD,
  * STFD_ST_BACK (back transform and update), STFD_ST_SPATIAL, STFD_ST_RESID,
- * STFD_ST_REDUCE (FP64 residual).
+ * STFD_ST_REDUCE (FP64 residual), STFD_ST_INNER (residual and update of the
+ * spatial solves' inner refinement; its sweeps count as sweeps).
  * stfd_profile(p, 1) enables and clears the accumulators, (p, 0) disables.
  * stfd_profile_read waits for the recorded events and returns, per stage, the
  * summed milliseconds and the number of launches since the last clear
  * (ms, counts: STFD_NSTAGE entries each, caller-owned).
  * ------------------------------------------------------------------------- */
-#define STFD_NSTAGE 10
+#define STFD_NSTAGE 11
 #define STFD_ST_BAND_INIT 0
 #define STFD_ST_BAND_LDL 1
 #define STFD_ST_FWD1 2
@@ -317,6 +384,7 @@ int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, const doubl
 #define STFD_ST_SPATIAL 7
 #define STFD_ST_RESID 8
 #define STFD_ST_REDUCE 9
+#define STFD_ST_INNER 10
 int stfd_profile(stfd_problem* p, int enable);
 int stfd_profile_read(stfd_problem* p, double* ms, long long* counts);
 

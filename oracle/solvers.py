@@ -10,17 +10,14 @@ Functions
   kh_matrix  the sparse K_h, written out with scipy's kron (tiny meshes).
   kh_apply   K_h vec(U) by the Kronecker identity.
   direct     sparse LU solve of the full K_h (textbook routine, tiny meshes).
-  fd         Algorithm FD of Sec. 4.4, as stated: (1a) eigendecomposition of
-             the pencil (M_t, A_t), (1b) SVD X = U_t Sigma V_t^*, (2) forward
-             transform G = F^ A_t^-1 conj(U_t) Sigma^-1 V_t^T, (3) the N_t
-             independent spatial solves (M_x + lambda_k A_x) z_k = g_k, (4) the
-             back transform U = Z conj(V_t) Sigma U_t^T.
+  fd         Alg. FD (Sec. 4.4): diagonalise the time pencil, change the
+             time basis of the load to the eigenvectors, solve one
+             independent spatial system per eigenvalue, change back.
   refine     FP64 iterative refinement: R = F~ - K_h u, u += FD(R).
   bartels_stewart
-             Algorithm BSc of Sec. 4.3, as stated: (1) complex Schur form
-             A_t^-1 M_t = W S W^*, (2) G = F^ A_t^-1 conj(W), (3) for
-             k = N_t .. 1 the spatial solve (M_x + S_kk A_x) z_k =
-             g_k - sum_{j>k} S_kj A_x z_j, (4) U = Re(Z W^T).
+             Alg. BSc (Sec. 4.3): triangularise the time pencil with a
+             unitary basis instead, then solve the spatial systems in
+             reverse order, each coupled to the ones already solved.
 
 Parity status: ``direct`` is a library routine on the written-out matrix;
 ``fd``, ``refine`` and ``bartels_stewart`` are pinned against it on small
@@ -111,43 +108,50 @@ def _spatial_solve(args):
 
 
 def fd(At, Mt, Mx, Ax, F, dec: Decomposition | None = None, pool_map=map):
-    """Algorithm FD (steps 1a-4); returns the real M_x x N_t solution U.
+    """Alg. FD; returns the real M_x x N_t solution U.
 
-    ``pool_map`` runs the N_t independent spatial solves of step 3 (the
-    paper solves them in parallel over the time modes); the default is the
-    builtin serial ``map``.
+    Why it works: with M_t X = A_t X diag(lambda), write U = Z X^T.  Then
+    M_x U A_t^T + A_x U M_t^T = (M_x Z + A_x Z diag(lambda)) (A_t X)^T, so
+    K_h u = F~ splits into one spatial system per eigenvalue,
+    (M_x + lambda_k A_x) z_k = g_k, for the columns g_k of
+    G = F~ (A_t X)^-T = F~ A_t^-1 X^-T.  X^-T is applied through the SVD
+    of X (X^-T = conj(U_t) Sigma^-1 V_t^T), as the paper does.
+
+    ``pool_map`` maps the independent spatial solves (the paper's time
+    parallelism); the default is the builtin serial ``map``.
     """
     if dec is None:
         dec = decompose(At, Mt)
     F = np.asarray(F, dtype=np.float64)
-    # step 2: G = F^ A_t^-1 conj(U_t) Sigma^-1 V_t^T
-    W = sl.cho_solve(dec.At_cho, dec.Ut.conj())          # A_t^-1 conj(U_t)
-    G = ((F @ W) / dec.sig[None, :]) @ dec.Vt.T
-    # step 3: (M_x + lambda_k A_x) z_k = g_k for every k, independently
+    # load in the eigenvector basis: F~ A_t^-1 X^-T, the SVD factors
+    # applied one after the other (A_t^-1 conj(U_t), then Sigma^-1, then V_t^T)
+    G = ((F @ sl.cho_solve(dec.At_cho, dec.Ut.conj())) / dec.sig[None, :]) @ dec.Vt.T
+    # one spatial system per eigenvalue
     cols = list(pool_map(_spatial_solve,
                          [(Mx, Ax, dec.lam[k], G[:, k]) for k in range(len(dec.lam))]))
     Z = np.stack(cols, axis=1)
-    # step 4: u = vec(Z conj(V_t) Sigma U_t^T)
-    Uc = ((Z @ dec.Vt.conj()) * dec.sig[None, :]) @ dec.Ut.T
-    return Uc.real
+    # back to the hat basis in time: U = Z X^T with X^T through the same
+    # factors (real for a real load)
+    return (((Z @ dec.Vt.conj()) * dec.sig[None, :]) @ dec.Ut.T).real
 
 
 def bartels_stewart(At, Mt, Mx, Ax, F):
-    """Algorithm BSc (Bartels-Stewart with the complex Schur form, Sec. 4.3);
-    returns the real M_x x N_t solution U."""
+    """Alg. BSc (Sec. 4.3); returns the real M_x x N_t solution U.
+
+    With the unitary triangularisation A_t^-1 M_t W = W S (S upper
+    triangular) and U = Z W^T, K_h u = F~ becomes
+    M_x Z + A_x Z S^T = F~ A_t^-1 conj(W) =: G; column k of that reads
+    (M_x + S_kk A_x) z_k = g_k - A_x sum_{j>k} S_kj z_j, so the columns are
+    solved from the last to the first."""
     At = np.asarray(At)
     F = np.asarray(F, dtype=np.float64)
-    # step 1: A_t^-1 M_t = W S W^*, W unitary, S upper triangular
     S, W = sl.schur(np.linalg.solve(At, np.asarray(Mt)), output="complex")
-    # step 2: G = F^ A_t^-1 conj(W)   (column k of G is g_k)
     G = F @ np.linalg.solve(At, W.conj())
-    # step 3: backward substitution over the triangular S, one spatial solve per k
     nt = At.shape[0]
     Z = np.zeros(G.shape, dtype=np.complex128)
     for k in range(nt - 1, -1, -1):
         rhs = G[:, k] - Ax @ (Z[:, k + 1:] @ S[k, k + 1:])
         Z[:, k] = _spatial_solve((Mx, Ax, S[k, k], rhs))
-    # step 4: u = (W (x) I) z, i.e. U = Z W^T (real up to rounding)
     return (Z @ W.T).real
 
 

@@ -22,6 +22,11 @@ struct stfd_space {
     // vertex numbers): the columns of M_x and A_x dropped for the boundary
     std::vector<int> rowptrB, colB;
     std::vector<double> valMB, valAB;
+    // envelope of the pivot-free LDL^T in blocks of 16: block_reach[c] =
+    // the number of 16-row blocks below diagonal block c that its columns'
+    // band reaches (every later L entry of those columns, fill included,
+    // lies in these blocks; at most ceil(half_band / 16))
+    std::vector<int> block_reach;
 };
 
 namespace stfd {

@@ -32,6 +32,9 @@ extern "C" int stfd_opts_default(stfd_opts* o) {
     o->rtol = 1e-10;
     o->max_refine = 30;
     o->method = STFD_METHOD_FD;
+    o->inner_refine = 0;
+    o->graph = 1;
+    o->nrhs_max = 0;
     return STFD_OK;
 }
 
@@ -118,6 +121,19 @@ extern "C" int stfd_space_create(int nv, const double* xy, int ntri, const int* 
         }
     }
     s->half_band = hb;
+    {
+        // the fill of column c stays above the last row any column k <= c
+        // reaches: reach(c) = max_{k <= c} (last row of column k)
+        const int nblk = (Mx + 15) / 16;
+        s->block_reach.assign(nblk, 0);
+        int last = -1;
+        for (int i = 0; i < Mx; ++i) {
+            for (int e = s->rowptr[i]; e < s->rowptr[i + 1]; ++e) last = std::max(last, s->col[e]);
+            last = std::max(last, i);
+            const int b = i / 16, lastblk = std::min(last, Mx - 1) / 16;
+            s->block_reach[b] = std::max(s->block_reach[b], lastblk - b);
+        }
+    }
     s->rowptrB.assign(Mx + 1, 0);
     for (int i = 0; i < Mx; ++i) {
         s->rowptrB[i + 1] = s->rowptrB[i] + (int)rowsB[i].size();

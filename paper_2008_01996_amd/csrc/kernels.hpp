@@ -25,7 +25,28 @@ struct GemmArgs {
     long long strideA, strideC, strideF;
     int batch;
     double alpha;
+    const int* gate;    // launch_gate() at launch: the kernel returns at once while *gate != 0
+    int bm;             // workgroup tile height: 64 (default) or 128 (not for EPI_RESID)
+    int nfast;          // 1: consecutive workgroups run along N (share an A panel)
 };
+
+// Gate of the kernels of a refinement round.  While a device flag is set as
+// the gate on the calling host thread, every launcher below passes it to its
+// kernel, which returns at once when the flag is nonzero: replays of a
+// captured round after the solve has converged do no work.
+void set_launch_gate(const int* gate);
+const int* launch_gate();
+
+// one refinement round ends with this check: norms (2 nrhs: ||R||^2, ||F||^2)
+// give the relative residual (max over the right-hand sides); ctl[0] = done,
+// ctl[1] = applications so far, ctl[2] = status (0 running, 1 converged,
+// 2 zero or non-finite pivot, 3 out of applications, 4 non-finite
+// residual); hist[a] = the
+// residual after application a.  Gated on ctl[0] itself.
+hipError_t launch_refine_check(const double* norms, int nrhs, double rtol, const int* pivot_flag, int max_apps,
+                               int* ctl, double* hist, hipStream_t st);
+// ctl[0..2] = 0, *flag = 0 (no memset nodes in captured graphs)
+hipError_t launch_reset_ints(int* p, int n, hipStream_t st);
 
 enum GemmKind {
     GEMM_D_D_STORE_D,   // FP64 in, FP64 MFMA, FP64 out
@@ -44,14 +65,27 @@ size_t gemm_resid_partials(int M, int N, int batch);
 
 hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, const int* col, const double* valM,
                                 const double* valA, const double* U, double* P, hipStream_t st);
+// G -= (M_x + lambda_k A_x) Z for every system and right-hand side (FP64 arithmetic on working-precision data)
+template <typename T>
+hipError_t launch_spatial_resid(int Mx, int nsys, int nrhs, const int* rowptr, const int* col, const double* valM,
+                                const double* valA, const double* lam, void* G, const void* Z, hipStream_t st);
+// y += x, n elements
+template <typename T>
+hipError_t launch_add(void* y, const void* x, size_t n, hipStream_t st);
 hipError_t launch_reduce_partials(const double* partial, size_t blocks, int nrhs, double* norms, hipStream_t st);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 
 template <typename T>
 hipError_t launch_band_init(void* LB, int Mx, int bp, int nsys, const int* rowptr, const int* col,
                             const double* valM, const double* valA, const double* lam, hipStream_t st);
+// factor kernel: automatic (the register window for FP32 with padded band
+// 128, the LDS window where it fits, else the panel kernel), or forced.  The
+// last nreal systems are real (every imaginary part zero): the panel kernel
+// factors them two to a workgroup in real arithmetic.
+enum { FACTOR_AUTO = 0, FACTOR_STREAM = 1, FACTOR_PANEL = 2 };
 template <typename T>
-hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStream_t st);
+hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int nreal, const int* reach, int* flag, int kernel,
+                           hipStream_t st);
 // sweeps of systems sys0 .. sys0 + nrun - 1 of the nsys (G, W laid out for all nsys)
 template <typename T>
 hipError_t launch_band_forward(const void* LB, int Mx, int bp, int nsys, int nrhs, const void* G, void* W,
@@ -64,6 +98,22 @@ hipError_t launch_band_backward(const void* LB, int Mx, int bp, int nsys, int nr
 // (S row-major nsys x nsys, complex interleaved)
 hipError_t launch_bs_update(int Mx, int nsys, int nrhs, int k, const int* rowptr, const int* col,
                             const double* valA, const double* S, double* G, hipStream_t st);
+// Tile sweeps (kernels_tile.hip): up to 16 right-hand sides per workgroup on
+// the matrix cores, with the inverses of the 16 x 16 diagonal blocks of L
+// (LI: n_sys x ceil(M_x / 16) blocks of 16 x 16, column-major).
+constexpr int TILE_BPMAX = 256;
+// the largest padded half-bandwidth any sweep kernel takes
+constexpr int BAND_BPMAX = 256;
+template <typename T>
+hipError_t launch_band_diag_inverse(const void* LB, void* LI, int Mx, int bp, int nsys, hipStream_t st);
+template <typename T>
+// reach[b]: 16-row blocks below diagonal block b that the factor's columns
+// reach (the envelope; blocks beyond are zero and skipped)
+hipError_t launch_tile_forward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
+                               const void* G, void* W, hipStream_t st, int sys0, int nrun);
+template <typename T>
+hipError_t launch_tile_backward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
+                                void* W, hipStream_t st, int sys0, int nrun);
 template <typename T>
 size_t band_ldl_smem(int bp);
 template <typename T>

@@ -15,6 +15,8 @@
 // contiguous in memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -394,7 +396,7 @@ __global__ void __launch_bounds__(256) band_ldl_window_kernel(cplx<T>* __restric
 // band rows 16B .. 16B + 127 (row blocks B .. B + 7) are eight 16x16 MFMA
 // accumulator tiles; tile ra (row block B + ra) is owned by tile wave
 // (B + ra / 2) mod 4, in that wave's slot 0 at positions 0-3 and slot 1 at
-// positions 4-7, and the trailing updates accumulate into it directly.  The
+// positions 4-7, and every trailing update is subtracted from it there.  The
 // shifts give every tile wave 9 of the 36 tiles a panel updates (owning
 // whole blocks would give 12, 10, 8 and 6) and two tiles of every block, so
 // that the update of the next block and its hand-over are spread evenly.  Row block B + 8 of the block is only touched by the
@@ -470,16 +472,21 @@ __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restri
         // C -= L_c D L_r^T on a tile: the columns are rows 16 m + li of the
         // previous panel's rows 16.. (m the block's position), the rows rows
         // 16 (m + ra) + li; operands from that panel's buffer Pp and its LD
+        // (the panel's contribution is summed on its own and subtracted once,
+        // so the accumulator tile rounds once per panel, not after every MFMA)
         auto tile_mfma = [&](V4& cr, V4& ci, const cplx<T>* Pp, const cplx<T>* LD, int m, int ra) {
+            V4 ur = zero4<T>(), ui = zero4<T>();
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
                 const int k = 4 * kk + lk;
                 const cplx<T> x = Pp[(16 + 16 * m + li) * RPS + k], y = LD[(16 * (m + ra) + li) * RPS + k];
-                cr = mfma16x16x4<T>(-x.re, y.re, cr);
-                ci = mfma16x16x4<T>(-x.re, y.im, ci);
-                cr = mfma16x16x4<T>(x.im, y.im, cr);
-                ci = mfma16x16x4<T>(-x.im, y.re, ci);
+                ur = mfma16x16x4<T>(x.re, y.re, ur);
+                ui = mfma16x16x4<T>(x.re, y.im, ui);
+                ur = mfma16x16x4<T>(-x.im, y.im, ur);
+                ui = mfma16x16x4<T>(x.im, y.re, ui);
             }
+            cr -= ur;
+            ci -= ui;
         };
 
         V4 accR[2][8], accI[2][8];
@@ -642,6 +649,237 @@ __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restri
 }
 
 // ---------------------------------------------------------------------------
+// Bands up to 256 with the panel in registers and the trailing tiles
+// streamed, one workgroup of 8 waves per system.  Panel q (columns p0 = 16 q
+// .. p0 + 15), with nr = reach[q] row blocks below its diagonal block (the
+// envelope of the factor: blocks further down are zero and stay zero):
+//  1. every lane that owns a panel row holds its 16 entries in registers
+//     (lanes 0-15 of every wave the rows of the diagonal block, lanes 16-47
+//     of wave w the rows p0 + 16 + 32 w + (lane - 16)); the rows the previous
+//     panel updated come from the hand-over buffer in LDS, the others from
+//     HBM, loaded a panel ahead;
+//  2. the panel is factored in registers with lane broadcasts, no barrier;
+//  3. the factored panel is written to HBM once, and its rows below the
+//     diagonal block (L) with D go to LDS, the operands of the update;
+//  4. the trailing tiles (ti, tj), tj <= ti < nr, are dealt round-robin to
+//     the 8 waves; a tile is read from HBM (the next one of the wave in
+//     flight meanwhile), updated on the matrix cores, C -= L_c (L_r D)^T as
+//     four real 16x16x4 MFMAs per complex k-step, and written back.  The
+//     tiles of column block q + 1 (tj = 0) are the next panel: they go to
+//     the hand-over buffer instead of HBM.
+// LDS: L rows [256][PS], hand-over [256][PS] (complex), D [16].
+// ---------------------------------------------------------------------------
+constexpr int PS = 17;                                    // LDS row stride (complex) of the panel buffers
+
+// One system; REAL: the system is real (lambda real, every imaginary part
+// zero), so only the real parts are computed (a quarter of the MFMAs) and the
+// stored imaginary parts stay zero.  The results are those of the complex
+// form on the same system: its imaginary terms are exact zeros.
+template <typename T, bool REAL>
+__device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, int Mx, int bp,
+                                                    const int* __restrict__ reach, int* __restrict__ flag,
+                                                    unsigned char* smem_raw) {
+    using V4 = typename vec4<T>::type;
+    cplx<T>* PL = reinterpret_cast<cplx<T>*>(smem_raw);   // L of the rows below the diagonal block
+    cplx<T>* NX = PL + 256 * PS;                          // hand-over: the next panel's updated rows
+    cplx<T>* PD = NX + 256 * PS;                          // D of the panel
+    const int bp1 = bp + 1;
+    const int NB = bp / 16;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int nblk = (Mx + 15) / 16;
+    const cplx<T> zero = {T(0), T(0)};
+    // this lane's panel row, relative to p0
+    const bool own = lane < 48;
+    const int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
+
+    // entry (p0 + rrel, p0 + c) of the band, clamped address, and whether it exists
+    auto ent_on = [&](int p0, int c, int nrow) {
+        const int d = rrel - c;
+        return own && rrel < nrow && d >= 0 && d <= bp && p0 + rrel < Mx && p0 + c < Mx;
+    };
+    auto ent_addr = [&](int p0, int c, int nrow) -> size_t {
+        return ent_on(p0, c, nrow) ? (size_t)(p0 + c) * bp1 + (rrel - c) : 0;
+    };
+    // raw loads of this lane's row of panel starting at p0 (rows < nrow)
+    cplx<T> pf[16];
+    auto prefetch = [&](int p0, int nrow) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const cplx<T>* e = base + ent_addr(p0, c, nrow);
+            pf[c].re = e->re;
+            pf[c].im = e->im;
+        }
+    };
+    int nr_prev = 0;                                      // row blocks the previous panel updated
+    prefetch(0, nblk > 0 ? 16 + 16 * min(NB, reach[0]) : 0);
+
+    for (int q = 0; q < nblk; ++q) {
+        const int p0 = 16 * q;
+        const int nb = min(16, Mx - p0);
+        const int nr = min(NB, reach[q]);
+        const int nrow = 16 + 16 * nr;                    // rows of the panel
+        // ---- 1. the panel row: hand-over buffer (rows the previous panel
+        // updated) or the prefetched HBM values
+        cplx<T> a[16];
+        const bool from_nx = rrel < 16 * nr_prev;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const bool on = ent_on(p0, c, nrow);
+            const cplx<T> x = NX[(from_nx ? rrel : 0) * PS + c];
+            a[c].re = on ? (from_nx ? x.re : pf[c].re) : T(0);
+            a[c].im = on ? (from_nx ? x.im : pf[c].im) : T(0);
+        }
+        // the next panel's rows this panel does not update: from HBM now
+        if (q + 1 < nblk) {
+            const int nrow1 = 16 + 16 * min(NB, reach[q + 1]);
+            // rows of panel q + 1 at or beyond 16 nr (relative to its start)
+            // are untouched by any earlier panel
+            if (rrel >= 16 * nr) prefetch(p0 + 16, nrow1);
+        }
+        // ---- 2. factor the panel in registers
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < nb) {
+                const cplx<T> dk = {lane_bcast(a[k].re, k), lane_bcast(a[k].im, k)};
+                const cplx<T> inv = cinv_fast(dk);
+                const T mag = fabs(dk.re) + fabs(dk.im);
+                bad |= int(!(mag > T(0))) | int(!isfinite(mag));
+                const cplx<T> aik = a[k];
+                if constexpr (REAL) {
+                    if (rrel > k) a[k].re = aik.re * inv.re;
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) a[j].re = fma(-aik.re, lane_bcast(a[k].re, j), a[j].re);
+                } else {
+                    if (rrel > k) a[k] = cmul(aik, inv);
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) {
+                        const T lr = lane_bcast(a[k].re, j), lim = lane_bcast(a[k].im, j);
+                        a[j].re = fma(-aik.re, lr, a[j].re);
+                        a[j].re = fma(aik.im, lim, a[j].re);
+                        a[j].im = fma(-aik.re, lim, a[j].im);
+                        a[j].im = fma(-aik.im, lr, a[j].im);
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        if (tid == 0 && bad != 0) atomicOr(flag, 1);
+        // ---- 3. write the panel out; L rows and D to LDS
+        const bool writer = own && (lane >= 16 || wave == 0);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (writer && c < nb && ent_on(p0, c, nrow)) base[(size_t)(p0 + c) * bp1 + (rrel - c)] = a[c];
+        if (own && lane >= 16) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) PL[(rrel - 16) * PS + c] = rrel < nrow ? a[c] : zero;
+        }
+        if (wave == 0 && lane < 16) PD[lane] = a[lane];
+        __syncthreads();
+        // ---- 4. trailing tiles, wave w takes tiles w, w + 8, ...
+        const int ntile = nr * (nr + 1) / 2;
+        auto tile_ij = [](int t, int& ti, int& tj) {
+            ti = 0;
+            while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+            tj = t - ti * (ti + 1) / 2;
+        };
+        // element j of this lane in tile (ti, tj): row r = p0 + 16 + 16 ti + li,
+        // column c' = p0 + 16 + 16 tj + mfma_row(lk, j)
+        auto c_on = [&](int ti, int tj, int j) {
+            const int r = p0 + 16 + 16 * ti + li, cc = p0 + 16 + 16 * tj + mfma_row<T>(lk, j);
+            const int d = r - cc;
+            return d >= 0 && d <= bp && r < Mx && cc < Mx;
+        };
+        auto c_load = [&](int t, cplx<T> (&cv)[4]) {
+            int ti, tj;
+            tile_ij(t < ntile ? t : 0, ti, tj);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = p0 + 16 + 16 * ti + li, cc = p0 + 16 + 16 * tj + mfma_row<T>(lk, j);
+                const cplx<T>* e = base + (t < ntile && c_on(ti, tj, j) ? (size_t)cc * bp1 + (r - cc) : 0);
+                cv[j].re = e->re;
+                cv[j].im = e->im;
+            }
+        };
+        auto c_update = [&](int t, const cplx<T> (&cv)[4]) {
+            int ti, tj;
+            tile_ij(t, ti, tj);
+            // the panel's contribution is summed on its own and subtracted
+            // once: C rounds once per panel, not after every MFMA
+            V4 ur = zero4<T>(), ui = zero4<T>();
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                if constexpr (REAL) {
+                    ur = mfma16x16x4<T>(PL[(16 * tj + li) * PS + k].re,
+                                        PL[(16 * ti + li) * PS + k].re * PD[k].re, ur);
+                } else {
+                    const cplx<T> x = PL[(16 * tj + li) * PS + k];              // column side: L
+                    const cplx<T> y = cmul(PL[(16 * ti + li) * PS + k], PD[k]);  // row side: L D
+                    ur = mfma16x16x4<T>(x.re, y.re, ur);
+                    ui = mfma16x16x4<T>(x.re, y.im, ui);
+                    ur = mfma16x16x4<T>(-x.im, y.im, ur);
+                    ui = mfma16x16x4<T>(x.im, y.re, ui);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!c_on(ti, tj, j)) continue;
+                const cplx<T> v = {cv[j].re - ur[j], cv[j].im - ui[j]};
+                if (tj == 0) {
+                    NX[(16 * ti + li) * PS + mfma_row<T>(lk, j)] = v;           // the next panel
+                } else {
+                    const int r = p0 + 16 + 16 * ti + li, cc = p0 + 16 + 16 * tj + mfma_row<T>(lk, j);
+                    base[(size_t)cc * bp1 + (r - cc)] = v;
+                }
+            }
+        };
+        {
+            cplx<T> c0[4], c1[4];
+            int t = wave;
+            c_load(t, c0);
+            // two tiles per round in straight-line code (each buffer a fixed
+            // set of registers), the next tile's loads in flight
+            while (t < ntile) {
+                c_load(t + 8, c1);
+                c_update(t, c0);
+                t += 8;
+                if (t >= ntile) break;
+                c_load(t + 8, c0);
+                c_update(t, c1);
+                t += 8;
+            }
+        }
+        nr_prev = nr;
+        __syncthreads();
+    }
+}
+
+// Systems [0, ncplx) complex, one per workgroup; systems [ncplx, nsys) real,
+// two per workgroup one after the other (each costs about a quarter of a
+// complex one), so that, e.g., 2 p + 2 systems make 2 p + 1 workgroups.
+template <typename T>
+__global__ void __launch_bounds__(512) band_ldl_panel_kernel(cplx<T>* __restrict__ LB, int Mx, int bp, int ncplx,
+                                                            int nsys, const int* __restrict__ reach,
+                                                            int* __restrict__ flag) {
+    extern __shared__ unsigned char smem_raw[];
+    const size_t stride = (size_t)Mx * (bp + 1);
+    const int b = blockIdx.x;
+    if (b < ncplx) {
+        panel_factor_system<T, false>(LB + (size_t)b * stride, Mx, bp, reach, flag, smem_raw);
+        return;
+    }
+    const int s0 = ncplx + 2 * (b - ncplx);
+    panel_factor_system<T, true>(LB + (size_t)s0 * stride, Mx, bp, reach, flag, smem_raw);
+    if (s0 + 1 < nsys) {
+        __syncthreads();
+        panel_factor_system<T, true>(LB + (size_t)(s0 + 1) * stride, Mx, bp, reach, flag, smem_raw);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -659,14 +897,42 @@ static size_t window_smem(int bp) { return ((size_t)(bp + 16) * (bp + 1) + 1) * 
 template <typename T>
 static bool use_window(int bp) { return bp <= 128 && window_smem<T>(bp) <= 150 * 1024; }
 
+static size_t stream_smem(int bp, size_t es) { return 2 * 16 * (size_t)(bp + 1) * es; }
+template <typename T>
+static size_t panel_smem() { return (2 * 256 * (size_t)PS + 16) * sizeof(cplx<T>); }
+
 template <typename T>
 size_t band_ldl_smem(int bp) {
-    return use_window<T>(bp) ? window_smem<T>(bp) : 2 * 16 * (size_t)(bp + 1) * sizeof(T);
+    return use_window<T>(bp) ? window_smem<T>(bp) : std::max(stream_smem(bp, sizeof(T)), panel_smem<T>());
 }
 
 template <typename T>
-hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int* flag, hipStream_t st) {
-    const size_t smem = band_ldl_smem<T>(bp);
+hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int nreal, const int* reach, int* flag,
+                           int kernel, hipStream_t st) {
+    if (nreal < 0 || nreal > nsys) return hipErrorInvalidValue;
+    // the panel kernel takes the trailing real systems in pairs
+    const int ncplx = nsys - nreal;
+    const int nwg = ncplx + (nreal + 1) / 2;
+    if (kernel == FACTOR_PANEL || (kernel == FACTOR_AUTO && !use_window<T>(bp) && !(sizeof(T) == 4 && bp == 128))) {
+        if (bp > 256 || bp % 16 != 0) return hipErrorInvalidValue;
+        const size_t smem = panel_smem<T>();
+        hipError_t e = hipFuncSetAttribute((const void*)band_ldl_panel_kernel<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(band_ldl_panel_kernel<T>, dim3(nwg), dim3(512), smem, st, static_cast<cplx<T>*>(LB), Mx, bp,
+                           ncplx, nsys, reach, flag);
+        return hipGetLastError();
+    }
+    if (kernel == FACTOR_STREAM) {
+        const size_t smem = stream_smem(bp, sizeof(T));
+        hipError_t e = hipFuncSetAttribute((const void*)band_ldl_kernel<T>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(band_ldl_kernel<T>, dim3(nsys), dim3(256), smem, st, static_cast<cplx<T>*>(LB), Mx, bp,
+                           flag);
+        return hipGetLastError();
+    }
+    const size_t smem = use_window<T>(bp) ? window_smem<T>(bp) : stream_smem(bp, sizeof(T));
     if constexpr (sizeof(T) == 4) {
         if (bp == 128) {
             hipLaunchKernelGGL(band_ldl_reg_kernel, dim3(nsys), dim3(512), 0, st, static_cast<cplx<float>*>(LB), Mx,
@@ -694,8 +960,8 @@ template hipError_t launch_band_init<float>(void*, int, int, int, const int*, co
                                             const double*, const double*, hipStream_t);
 template hipError_t launch_band_init<double>(void*, int, int, int, const int*, const int*, const double*,
                                              const double*, const double*, hipStream_t);
-template hipError_t launch_band_ldl<float>(void*, int, int, int, int*, hipStream_t);
-template hipError_t launch_band_ldl<double>(void*, int, int, int, int*, hipStream_t);
+template hipError_t launch_band_ldl<float>(void*, int, int, int, int, const int*, int*, int, hipStream_t);
+template hipError_t launch_band_ldl<double>(void*, int, int, int, int, const int*, int*, int, hipStream_t);
 template size_t band_ldl_smem<float>(int);
 template size_t band_ldl_smem<double>(int);
 

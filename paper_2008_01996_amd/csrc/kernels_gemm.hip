@@ -13,42 +13,55 @@
 // column-major stores).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace stfd {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BN = 64, BK = 16;
 
-template <typename TA, typename TC, int EPI>
+// TM 16-row MFMA tiles per wave along M: the workgroup tile is (32 TM) x 64
+// (TM = 2: 64 x 64, TM = 4: 128 x 64).  NFAST: blockIdx.x runs over the N
+// tiles (the workgroups that share an A panel run side by side) instead of
+// the M tiles.
+template <typename TA, typename TC, int EPI, int TM, bool NFAST>
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
-    __shared__ TC As[BK][BM];
+    if (g.gate && *g.gate) return;
+    constexpr int BMT = 32 * TM;
+    constexpr int RA = BMT / 64;                 // A rows per thread and k
+    __shared__ TC As[BK][BMT];
     __shared__ TC Bs[BK][BN];
     __shared__ double red[8];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int m0 = (NFAST ? blockIdx.y : blockIdx.x) * BMT, n0 = (NFAST ? blockIdx.x : blockIdx.y) * BN;
     const int batch = blockIdx.z;
     const TA* A = static_cast<const TA*>(g.A) + (size_t)batch * g.strideA;
     const TC* B = static_cast<const TC*>(g.B);
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int wm = (wave & 1) * (16 * TM), wn = (wave >> 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
 
-    typename vec4<TC>::type acc[2][2];
+    typename vec4<TC>::type acc[2][TM];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = zero4<TC>();
+        for (int b = 0; b < TM; ++b) acc[a][b] = zero4<TC>();
 
     // global -> registers for the K step at k0 (A coalesced along m, B along
     // n); the next step's loads are in flight while this one computes
-    TC ra[4], rb[4];
+    TC ra[4][RA], rb[4];
     auto load = [&](int k0) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = tid & 63, k = (tid >> 6) + 4 * i;
-            const int gm = m0 + m, gk = k0 + k;
-            ra[i] = gm < g.M && gk < g.K ? static_cast<TC>(A[(size_t)gm + (size_t)gk * g.lda]) : TC(0);
+            const int gk = k0 + k;
+#pragma unroll
+            for (int r = 0; r < RA; ++r) {
+                const int gm = m0 + m + 64 * r;
+                ra[i][r] = gm < g.M && gk < g.K ? static_cast<TC>(A[(size_t)gm + (size_t)gk * g.lda]) : TC(0);
+            }
             const int gn = n0 + m;
             rb[i] = gn < g.N && gk < g.K ? B[(size_t)gk * g.ldb + gn] : TC(0);
         }
@@ -58,7 +71,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int m = tid & 63, k = (tid >> 6) + 4 * i;
-            As[k][m] = ra[i];
+#pragma unroll
+            for (int r = 0; r < RA; ++r) As[k][m + 64 * r] = ra[i][r];
             Bs[k][m] = rb[i];
         }
         __syncthreads();
@@ -66,15 +80,15 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
             const int k = 4 * kk + lk;
-            TC bf[2], af[2];
+            TC bf[2], af[TM];
 #pragma unroll
             for (int t = 0; t < 2; ++t) bf[t] = Bs[k][wn + 16 * t + li];
 #pragma unroll
-            for (int t = 0; t < 2; ++t) af[t] = As[k][wm + 16 * t + li];
+            for (int t = 0; t < TM; ++t) af[t] = As[k][wm + 16 * t + li];
 #pragma unroll
             for (int tn = 0; tn < 2; ++tn)
 #pragma unroll
-                for (int tm = 0; tm < 2; ++tm) acc[tn][tm] = mfma16x16x4<TC>(bf[tn], af[tm], acc[tn][tm]);
+                for (int tm = 0; tm < TM; ++tm) acc[tn][tm] = mfma16x16x4<TC>(bf[tn], af[tm], acc[tn][tm]);
         }
         __syncthreads();
     }
@@ -84,7 +98,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 #pragma unroll
     for (int tn = 0; tn < 2; ++tn)
 #pragma unroll
-        for (int tm = 0; tm < 2; ++tm)
+        for (int tm = 0; tm < TM; ++tm)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m = m0 + wm + 16 * tm + li;
@@ -113,17 +127,30 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
         if (tid == 0) {
             const size_t blocks = (size_t)gridDim.x * gridDim.y;
             const size_t idx = (size_t)batch * blocks + (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+            // (the partials of a RHS are summed in full, in any block order)
             g.partial[2 * idx] = tr;
             g.partial[2 * idx + 1] = tf;
         }
     }
 }
 
-template <typename TA, typename TC, int EPI>
-static hipError_t launch_gemm_t(const GemmArgs& g, hipStream_t st) {
-    dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN, g.batch);
-    hipLaunchKernelGGL((gemm_kernel<TA, TC, EPI>), grid, dim3(256), 0, st, g);
+template <typename TA, typename TC, int EPI, int TM, bool NFAST>
+static hipError_t launch_gemm_v(const GemmArgs& g, hipStream_t st) {
+    const unsigned mt = (g.M + 32 * TM - 1) / (32 * TM), nt = (g.N + BN - 1) / BN;
+    dim3 grid(NFAST ? nt : mt, NFAST ? mt : nt, g.batch);
+    hipLaunchKernelGGL((gemm_kernel<TA, TC, EPI, TM, NFAST>), grid, dim3(256), 0, st, g);
     return hipGetLastError();
+}
+
+// variant by the tile height (bm = 64 or 128) and the grid order
+template <typename TA, typename TC, int EPI>
+static hipError_t launch_gemm_t(const GemmArgs& g0, hipStream_t st) {
+    GemmArgs g = g0;
+    g.gate = launch_gate();
+    if (EPI == EPI_RESID && g.bm == 128) g.bm = 64;   // its partials are counted for the 64-row tile
+    if (g.bm == 128)
+        return g.nfast ? launch_gemm_v<TA, TC, EPI, 4, true>(g, st) : launch_gemm_v<TA, TC, EPI, 4, false>(g, st);
+    return g.nfast ? launch_gemm_v<TA, TC, EPI, 2, true>(g, st) : launch_gemm_v<TA, TC, EPI, 2, false>(g, st);
 }
 
 hipError_t launch_gemm(GemmKind kind, const GemmArgs& g, hipStream_t st) {
@@ -142,7 +169,7 @@ hipError_t launch_gemm(GemmKind kind, const GemmArgs& g, hipStream_t st) {
 }
 
 size_t gemm_resid_partials(int M, int N, int batch) {
-    return (size_t)((M + BM - 1) / BM) * ((N + BN - 1) / BN) * batch;
+    return (size_t)((M + 63) / 64) * ((N + BN - 1) / BN) * batch;
 }
 
 // ---------------------------------------------------------------------------
@@ -160,7 +187,9 @@ __global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, cons
                                                             const int* __restrict__ col,
                                                             const double* __restrict__ valM,
                                                             const double* __restrict__ valA,
-                                                            const double* __restrict__ U, double* __restrict__ P) {
+                                                            const double* __restrict__ U, double* __restrict__ P,
+                                                            const int* __restrict__ gate) {
+    if (gate && *gate) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int k0 = blockIdx.y * SPATIAL_KC;
     const int batch = blockIdx.z;
@@ -200,9 +229,79 @@ __global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, cons
 hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, const int* col, const double* valM,
                                 const double* valA, const double* U, double* P, hipStream_t st) {
     dim3 grid((Mx + 255) / 256, (Nt + SPATIAL_KC - 1) / SPATIAL_KC, nrhs);
-    hipLaunchKernelGGL(spatial_apply_kernel<8>, grid, dim3(256), 0, st, Mx, Nt, rowptr, col, valM, valA, U, P);
+    hipLaunchKernelGGL(spatial_apply_kernel<8>, grid, dim3(256), 0, st, Mx, Nt, rowptr, col, valM, valA, U, P,
+                       launch_gate());
     return hipGetLastError();
 }
+
+// Residual of the spatial systems of step 3 of Algorithm FD, for one step of
+// refinement inside an application: R = G - (M_x + lambda_k A_x) Z for every
+// system k and right-hand side, with the CSR products and the subtraction in
+// FP64 from the stored (working-precision) G and Z; R overwrites G.  Layout of
+// G, Z per RHS: column-major M_x x 2 n_sys, real parts of system k in column
+// k, imaginary parts in column n_sys + k.  One thread per row; grid.y runs
+// over the systems, grid.z over the right-hand sides.
+template <typename T>
+__global__ void __launch_bounds__(256) spatial_resid_kernel(int Mx, int nsys, const int* __restrict__ rowptr,
+                                                            const int* __restrict__ col,
+                                                            const double* __restrict__ valM,
+                                                            const double* __restrict__ valA,
+                                                            const double* __restrict__ lam, T* __restrict__ G,
+                                                            const T* __restrict__ Z, const int* __restrict__ gate) {
+    if (gate && *gate) return;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Mx) return;
+    const int k = blockIdx.y;
+    const size_t rhs = (size_t)blockIdx.z * 2 * nsys * Mx;
+    const T* zr = Z + rhs + (size_t)k * Mx;
+    const T* zi = Z + rhs + (size_t)(nsys + k) * Mx;
+    T* gr = G + rhs + (size_t)k * Mx;
+    T* gi = G + rhs + (size_t)(nsys + k) * Mx;
+    const double lr = lam[2 * k], li = lam[2 * k + 1];
+    double sr = 0.0, si = 0.0;
+    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
+        const int j = col[e];
+        const double mr = valM[e] + lr * valA[e], mi = li * valA[e];
+        const double xr = static_cast<double>(zr[j]), xi = static_cast<double>(zi[j]);
+        sr += mr * xr - mi * xi;
+        si += mr * xi + mi * xr;
+    }
+    gr[i] = static_cast<T>(static_cast<double>(gr[i]) - sr);
+    gi[i] = static_cast<T>(static_cast<double>(gi[i]) - si);
+}
+
+template <typename T>
+hipError_t launch_spatial_resid(int Mx, int nsys, int nrhs, const int* rowptr, const int* col, const double* valM,
+                                const double* valA, const double* lam, void* G, const void* Z, hipStream_t st) {
+    dim3 grid((Mx + 255) / 256, nsys, nrhs);
+    hipLaunchKernelGGL(spatial_resid_kernel<T>, grid, dim3(256), 0, st, Mx, nsys, rowptr, col, valM, valA, lam,
+                       static_cast<T*>(G), static_cast<const T*>(Z), launch_gate());
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) add_kernel(T* __restrict__ y, const T* __restrict__ x, size_t n,
+                                                  const int* __restrict__ gate) {
+    if (gate && *gate) return;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
+template <typename T>
+hipError_t launch_add(void* y, const void* x, size_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(add_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<T*>(y),
+                       static_cast<const T*>(x), n, launch_gate());
+    return hipGetLastError();
+}
+
+template hipError_t launch_spatial_resid<float>(int, int, int, const int*, const int*, const double*, const double*,
+                                                const double*, void*, const void*, hipStream_t);
+template hipError_t launch_spatial_resid<double>(int, int, int, const int*, const int*, const double*,
+                                                 const double*, const double*, void*, const void*, hipStream_t);
+template hipError_t launch_add<float>(void*, const void*, size_t, hipStream_t);
+template hipError_t launch_add<double>(void*, const void*, size_t, hipStream_t);
 
 // Bartels-Stewart with the complex Schur form (Alg. BSc, Sec. 4.3), step 3:
 // once z_k is solved, the right-hand sides of the systems still to come take
@@ -242,7 +341,9 @@ hipError_t launch_bs_update(int Mx, int nsys, int nrhs, int k, const int* rowptr
 
 // fixed-order reduction of the residual GEMM partial sums: norms[2 r] =
 // ||R_r||^2, norms[2 r + 1] = ||F_r||^2
-__global__ void reduce_partials_kernel(const double* __restrict__ partial, size_t blocks, double* __restrict__ norms) {
+__global__ void reduce_partials_kernel(const double* __restrict__ partial, size_t blocks, double* __restrict__ norms,
+                                       const int* __restrict__ gate) {
+    if (gate && *gate) return;
     __shared__ double red[8];
     const int batch = blockIdx.x;
     double a = 0.0, b = 0.0;
@@ -259,7 +360,7 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partial, size_
 }
 
 hipError_t launch_reduce_partials(const double* partial, size_t blocks, int nrhs, double* norms, hipStream_t st) {
-    hipLaunchKernelGGL(reduce_partials_kernel, dim3(nrhs), dim3(256), 0, st, partial, blocks, norms);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3(nrhs), dim3(256), 0, st, partial, blocks, norms, launch_gate());
     return hipGetLastError();
 }
 
@@ -272,6 +373,57 @@ hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
     const size_t blocks = std::min<size_t>((n + 255) / 256, 8192);
     hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gate of a refinement round and the device-side convergence check
+// ---------------------------------------------------------------------------
+static thread_local const int* g_launch_gate = nullptr;
+
+void set_launch_gate(const int* gate) { g_launch_gate = gate; }
+const int* launch_gate() { return g_launch_gate; }
+
+__global__ void refine_check_kernel(const double* __restrict__ norms, int nrhs, double rtol,
+                                    const int* __restrict__ pivot_flag, int max_apps, int* __restrict__ ctl,
+                                    double* __restrict__ hist) {
+    if (ctl[0]) return;
+    if (threadIdx.x != 0) return;
+    double rel = 0.0;
+    bool finite = true;
+    for (int q = 0; q < nrhs; ++q) {
+        const double rr = norms[2 * q], ff = norms[2 * q + 1];
+        if (!isfinite(rr)) finite = false;
+        rel = fmax(rel, ff > 0.0 ? sqrt(rr / ff) : sqrt(rr));
+    }
+    const int a = ctl[1];
+    hist[a] = rel;
+    ctl[1] = a + 1;
+    int status = 0;
+    if (pivot_flag && *pivot_flag) status = 2;
+    else if (!finite) status = 4;
+    else if (rel <= rtol) status = 1;
+    else if (a + 1 >= max_apps) status = 3;
+    if (status) {
+        ctl[2] = status;
+        ctl[0] = 1;
+    }
+}
+
+hipError_t launch_refine_check(const double* norms, int nrhs, double rtol, const int* pivot_flag, int max_apps,
+                               int* ctl, double* hist, hipStream_t st) {
+    hipLaunchKernelGGL(refine_check_kernel, dim3(1), dim3(64), 0, st, norms, nrhs, rtol, pivot_flag, max_apps, ctl,
+                       hist);
+    return hipGetLastError();
+}
+
+__global__ void reset_ints_kernel(int* __restrict__ p, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
+}
+
+hipError_t launch_reset_ints(int* p, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(reset_ints_kernel, dim3(1), dim3(64), 0, st, p, n);
     return hipGetLastError();
 }
 

@@ -44,7 +44,7 @@ constexpr int NRS = 8;       // right-hand sides per workgroup
 // right-hand side and bp = BPC (every LDS offset a compile-time constant)
 constexpr int MODE_ANY = 0, MODE_MULTI = 1, MODE_ONE = 2, MODE_ONE_EXACT = 3;
 constexpr int NSLOT = 3;     // LDS block slots
-constexpr int BPMAX = 256;   // largest padded half-bandwidth
+constexpr int BPMAX = BAND_BPMAX;   // largest padded half-bandwidth
 
 // NTH threads per workgroup: wave 0 runs the critical path, the NL lanes of
 // the other NLW waves load blocks and apply the far band.
@@ -352,7 +352,8 @@ __device__ __forceinline__ void chain2(T& vr, T& vi, T& ar, T& ai, const cplx<T>
 template <typename T, int CB, int BPC, int MODE, int NTH>
 __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp_in,
                                                            int nsys, int nrhs, const T* __restrict__ G,
-                                                           T* __restrict__ W, int sys0) {
+                                                           T* __restrict__ W, int sys0, const int* __restrict__ gate) {
+    if (gate && *gate) return;
     using C = Cfg<T, CB, BPC, NTH>;
     constexpr bool ONE = MODE == MODE_ONE || MODE == MODE_ONE_EXACT;
     const int bp = MODE == MODE_ONE_EXACT ? BPC : bp_in;
@@ -578,7 +579,9 @@ __global__ void __launch_bounds__(NTH) sweep_forward_kernel(const cplx<T>* __res
 // ---------------------------------------------------------------------------
 template <typename T, int CB, int BPC, int MODE, int NTH>
 __global__ void __launch_bounds__(NTH) sweep_backward_kernel(const cplx<T>* __restrict__ LB, int Mx, int bp_in,
-                                                            int nsys, int nrhs, T* __restrict__ W, int sys0) {
+                                                            int nsys, int nrhs, T* __restrict__ W, int sys0,
+                                                            const int* __restrict__ gate) {
+    if (gate && *gate) return;
     using C = Cfg<T, CB, BPC, NTH>;
     constexpr bool ONE = MODE == MODE_ONE || MODE == MODE_ONE_EXACT;
     const int bp = MODE == MODE_ONE_EXACT ? BPC : bp_in;
@@ -774,7 +777,7 @@ static hipError_t launch_fwd(const void* LB, int Mx, int bp, int nsys, int nrhs,
     dim3 grid(nrun, (nrhs + NRS - 1) / NRS);
     hipLaunchKernelGGL((sweep_forward_kernel<T, CB, BPC, MODE, NTH>), grid, dim3(NTH), smem, st,
                        static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<const T*>(G),
-                       static_cast<T*>(W), sys0);
+                       static_cast<T*>(W), sys0, launch_gate());
     return hipGetLastError();
 }
 
@@ -787,7 +790,7 @@ static hipError_t launch_bwd(const void* LB, int Mx, int bp, int nsys, int nrhs,
     if (e != hipSuccess) return e;
     dim3 grid(nrun, (nrhs + NRS - 1) / NRS);
     hipLaunchKernelGGL((sweep_backward_kernel<T, CB, BPC, MODE, NTH>), grid, dim3(NTH), smem, st,
-                       static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W), sys0);
+                       static_cast<const cplx<T>*>(LB), Mx, bp, nsys, nrhs, static_cast<T*>(W), sys0, launch_gate());
     return hipGetLastError();
 }
 

@@ -1,0 +1,399 @@
+// Substitution sweeps of step 3 of Algorithm FD (Sec. 4.4) for a group of up
+// to 16 right-hand sides, on the matrix cores.  With the band factors
+// M_x + lambda_k A_x = L_k D_k L_k^T (kernels_band.hip) the sweeps are, per
+// system k and block of 16 columns c (blocks of 16 rows and columns, the
+// band reaching NB = bp / 16 blocks below the diagonal):
+//
+//   forward   y_c = L_cc^-1 (g_c - sum_{j<c} L_cj y_j),   w_c = D_c^-1 y_c
+//   backward  z_c = L_cc^-T (w_c - sum_{j>c} L_jc^T z_j)
+//
+// written right-looking: as soon as block c is solved, the pending sums of
+// the NB blocks it couples to take its contribution, a complex 16 x 16 x 16
+// product per block (four real 16x16x4 MFMAs per k-step of four).  The
+// pending 16-row x 16-right-hand-side tiles live in MFMA accumulator
+// registers: block j belongs to wave j mod 4 for the whole sweep, which
+// holds its next S = ceil(NB / 4) blocks in order.  The diagonal solve uses
+// the inverse of the unit-triangular diagonal block (computed once after the
+// factorization, band_diag_inverse_kernel), so it is one more tile product.
+//
+// Step for block c (one workgroup barrier):
+//   owner wave (c mod 4): its first tile is complete; it goes through LDS
+//     into the operand layout, is multiplied by L_cc^-1 (or L_cc^-T), the
+//     result is stored (forward: times D_c^-1) and written to LDS for the
+//     other waves; the owner's tiles move up one slot and the block that
+//     enters the window (c + 4S forward, c - 4S backward) takes the last;
+//   all waves: each pending tile j takes -= Q_jc x_c, Q_jc = L_jc (forward)
+//     or L_cj^T (backward), its operands loaded from the band storage
+//     straight into registers NSET steps ahead.
+// Every factor entry is read once for all right-hand sides of the group.
+//
+// Layouts: band storage LB[k][c][d] = L_k[c + d, c] (d = 0: D_k), padded
+// half-bandwidth bp (multiple of 16); block inverses LI[k][b][kc][m] =
+// (L_bb^-1)[m][kc] (column-major 16 x 16); right-hand sides per RHS t a
+// column-major M_x x 2 n_sys block at t * M_x * 2 n_sys, real parts of system
+// k in column k, imaginary parts in column n_sys + k.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace stfd {
+
+namespace {
+
+constexpr int TB = 16;        // block size (rows, columns, right-hand sides)
+constexpr int NWAVE = 4;
+constexpr int XS = TB + 1;    // LDS row stride of the transposed tiles
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Inverses of the unit lower triangular diagonal blocks, computed in FP64
+// from the stored factor: LI[k][b] column m is the solution of L_bb x = e_m
+// (rows and columns past M_x give the identity).  Eight blocks per workgroup,
+// one thread per column.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(128) band_diag_inverse_kernel(const cplx<T>* __restrict__ LB, cplx<T>* __restrict__ LI,
+                                                               int Mx, int bp, int nblk, long long nblocks) {
+    __shared__ double SR[8][TB][XS], SI[8][TB][XS];
+    const int q = threadIdx.x / TB, m = threadIdx.x % TB;
+    const long long gb = (long long)blockIdx.x * 8 + q;
+    const bool live = gb < nblocks;
+    const long long sys = live ? gb / nblk : 0;
+    const int b = live ? (int)(gb % nblk) : 0;
+    const int bp1 = bp + 1;
+    const int c = TB * b + m;
+    const cplx<T>* colp = LB + ((size_t)sys * Mx + (size_t)min(c, Mx - 1)) * bp1;
+#pragma unroll
+    for (int r = 0; r < TB; ++r) {
+        const int d = r - m;
+        const bool on = live && d > 0 && c < Mx && TB * b + r < Mx;
+        const cplx<T> v = on ? colp[d] : cplx<T>{T(0), T(0)};
+        SR[q][r][m] = static_cast<double>(v.re);
+        SI[q][r][m] = static_cast<double>(v.im);
+    }
+    __syncthreads();
+    double xr[TB], xi[TB];
+#pragma unroll
+    for (int r = 0; r < TB; ++r) {
+        double ar = r == m ? 1.0 : 0.0, ai = 0.0;
+#pragma unroll
+        for (int k = 0; k < r; ++k) {
+            const double lr = SR[q][r][k], li = SI[q][r][k];
+            ar -= lr * xr[k] - li * xi[k];
+            ai -= lr * xi[k] + li * xr[k];
+        }
+        xr[r] = ar;
+        xi[r] = ai;
+    }
+    if (live) {
+        cplx<T>* dst = LI + (size_t)gb * TB * TB + (size_t)m * TB;
+#pragma unroll
+        for (int r = 0; r < TB; ++r) dst[r] = cplx<T>{static_cast<T>(xr[r]), static_cast<T>(xi[r])};
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The tile sweep.  S slots per wave (ceil(NB / 4)), NSET register sets of
+// prefetched factor operands.
+// ---------------------------------------------------------------------------
+template <typename T, bool FWD, int S, int NSET>
+__global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restrict__ LB,
+                                                        const cplx<T>* __restrict__ LI, int Mx, int bp, int nsys,
+                                                        int nrhs, const T* __restrict__ Vin, T* __restrict__ Vout,
+                                                        int sys0, const int* __restrict__ reach,
+                                                        const int* __restrict__ gate) {
+    if (gate && *gate) return;
+    using V4 = typename vec4<T>::type;
+    __shared__ T XR[NWAVE][TB][XS], XI[NWAVE][TB][XS];    // owner's tile in operand layout
+    __shared__ T YR[2][TB][XS], YI[2][TB][XS];            // solved block, by step parity
+    const int bp1 = bp + 1;
+    const int NB = bp / TB;
+    const int nblk = (Mx + TB - 1) / TB;
+    const int sys = sys0 + blockIdx.x;
+    const int r0 = blockIdx.y * TB;
+    const int nr = min(TB, nrhs - r0);
+    const int tid = threadIdx.x;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int g = lane >> 4, n = lane & 15;
+    const bool nlive = n < nr;
+    const size_t rstride = (size_t)Mx * 2 * nsys;
+    const size_t voff = (size_t)(r0 + (nlive ? n : 0)) * rstride;
+    const T* vin_re = Vin + voff + (size_t)sys * Mx;
+    const T* vin_im = Vin + voff + (size_t)(nsys + sys) * Mx;
+    T* vout_re = Vout + voff + (size_t)sys * Mx;
+    T* vout_im = Vout + voff + (size_t)(nsys + sys) * Mx;
+    const cplx<T>* base = LB + (size_t)sys * Mx * bp1;
+    const cplx<T>* libase = LI + (size_t)sys * nblk * TB * TB;
+
+    // tile of the input vector for block j, accumulator layout.  The loads
+    // are issued raw (address clamped) so that they stay in flight;
+    // tile_mask zeroes the entries outside (rows past M_x, right-hand sides
+    // past nr, blocks outside the matrix) where the values are used.
+    auto tile_on = [&](int j, int r) {
+        const int row = TB * j + mfma_row<T>(g, r);
+        return nlive && j >= 0 && j < nblk && row < Mx;
+    };
+    auto load_tile_raw = [&](int j, V4& ar, V4& ai) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int rr = tile_on(j, r) ? TB * j + mfma_row<T>(g, r) : 0;
+            ar[r] = vin_re[rr];
+            ai[r] = vin_im[rr];
+        }
+    };
+    auto tile_mask = [&](int j, V4& ar, V4& ai) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool on = tile_on(j, r);
+            ar[r] = on ? ar[r] : T(0);
+            ai[r] = on ? ai[r] : T(0);
+        }
+    };
+    auto load_tile = [&](int j, V4& ar, V4& ai) {
+        load_tile_raw(j, ar, ai);
+        tile_mask(j, ar, ai);
+    };
+    // operand of Q_jc for k-step kk (lane: m = n, k = 4 kk + g), raw value
+    // (address clamped) and whether it lies in the band
+    // Factor operand of Q_jc for k-step kk (lane: m = n, k = 4 kk + g):
+    // forward L[16 j + m][16 c + k], backward L[16 c + k][16 j + m].  In the
+    // band storage its index is linear in the blocks,
+    //   forward  (16 c + 4 kk + g)(bp + 1) + 16 (j - c) + n - 4 kk - g
+    //          = 16 bp c + 16 j + n + (4 kk + g) bp,
+    //   backward 16 bp j + n bp + 16 c + 4 kk + g,
+    // and always in range except in the last block (clamped).  Entries of
+    // rows past M_x are zero in the storage; only the last tile of the band
+    // (d > bp there for some lanes) and columns past M_x need masking where
+    // the value is used (q_on).
+    const int qlast = Mx * bp1 - 1;
+    auto q_index = [&](int j, int c, int kk) -> int {
+        const int i = FWD ? TB * bp * c + TB * j + n + (4 * kk + g) * bp
+                          : TB * bp * j + n * bp + TB * c + 4 * kk + g;
+        return min(max(i, 0), qlast);
+    };
+    auto q_on = [&](int j, int c, int kk) {
+        const int d = FWD ? TB * (j - c) + n - 4 * kk - g : TB * (c - j) + 4 * kk + g - n;
+        const int col = FWD ? TB * c + 4 * kk + g : TB * j + n;
+        return d <= bp && col < Mx;
+    };
+    // whether block column c couples to block j (within the band and the
+    // envelope of the factor: reach[b] blocks below diagonal block b)
+    auto couples = [&](int j, int c) {
+        return FWD ? (j > c && j < nblk && j - c <= min(NB, reach[c]))
+                   : (j < c && j >= 0 && c - j <= min(NB, reach[j]));
+    };
+    // operand of the diagonal inverse for k-step kk: forward L_cc^-1[m][k],
+    // backward L_cc^-1[k][m]
+    auto li_addr = [&](int c, int kk) -> size_t {
+        const int cc = min(max(c, 0), nblk - 1);
+        const int m = n, k = 4 * kk + g;
+        return (size_t)cc * TB * TB + (FWD ? (size_t)k * TB + m : (size_t)m * TB + k);
+    };
+
+    // ---- this wave's pending tiles
+    V4 accR[S], accI[S];
+    const int j0 = FWD ? w : nblk - 1 - ((nblk - 1 - w) & 3);   // first block of this wave (may be < 0)
+#pragma unroll
+    for (int t = 0; t < S; ++t) load_tile(FWD ? j0 + 4 * t : j0 - 4 * t, accR[t], accI[t]);
+
+    // Everything step s needs from memory is loaded NSET steps ahead, by
+    // every wave alike (so the counts of outstanding loads are the same on
+    // every path and the waits stay exact): the factor operands of the
+    // wave's pending tiles, the data the owner of block c needs (the
+    // diagonal inverse, the tile entering when c retires; the other waves
+    // load it too and drop it), and D of the rows of block c this wave
+    // stores (forward).
+    cplx<T> qa[NSET][S][4], pa[NSET][4], da[NSET];
+    V4 ea[NSET][2];
+    auto fetch = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2]) {
+        const int c = FWD ? s : nblk - 1 - s;
+        const int delta = FWD ? ((w - c - 1) & 3) + 1 : ((c - w - 1) & 3) + 1;
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+            const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const cplx<T>* e = base + q_index(j, c, kk);
+                qx[t][kk].re = e->re;                 // raw: masked where used
+                qx[t][kk].im = e->im;
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const cplx<T>* e = libase + li_addr(c, kk);
+            px[kk].re = e->re;
+            px[kk].im = e->im;
+        }
+        load_tile_raw(FWD ? c + 4 * S : c - 4 * S, ex[0], ex[1]);
+        if (FWD) {
+            const int row = min(max(TB * c + 4 * w + g, 0), Mx - 1);
+            const cplx<T>* e = base + (size_t)row * bp1;
+            dx.re = e->re;
+            dx.im = e->im;
+        }
+    };
+#pragma unroll
+    for (int u = 0; u < NSET; ++u) fetch(u, qa[u], pa[u], da[u], ea[u]);
+
+    // one step: block c = (FWD ? s : nblk - 1 - s); steps past the end only fetch
+    auto step = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2]) {
+        const int c = FWD ? s : nblk - 1 - s;
+        const int par = s & 1;
+        if (s < nblk) {
+            if ((c & 3) == w) {
+                // ---- owner: x_c = P_c acc[0], to LDS for every wave
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    XR[w][mfma_row<T>(g, r)][n] = accR[0][r];
+                    XI[w][mfma_row<T>(g, r)][n] = accI[0][r];
+                }
+                wave_lds_sync();
+                V4 xr = zero4<T>(), xi = zero4<T>();
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const T br = XR[w][4 * kk + g][n], bi = XI[w][4 * kk + g][n];
+                    const cplx<T> a = px[kk];
+                    xr = mfma16x16x4<T>(a.re, br, xr);
+                    xr = mfma16x16x4<T>(-a.im, bi, xr);
+                    xi = mfma16x16x4<T>(a.re, bi, xi);
+                    xi = mfma16x16x4<T>(a.im, br, xi);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    YR[par][mfma_row<T>(g, r)][n] = xr[r];
+                    YI[par][mfma_row<T>(g, r)][n] = xi[r];
+                }
+                // slots move up; the entering block takes the last one
+#pragma unroll
+                for (int t = 0; t + 1 < S; ++t) {
+                    accR[t] = accR[t + 1];
+                    accI[t] = accI[t + 1];
+                }
+                V4 er = ex[0], ei = ex[1];
+                tile_mask(FWD ? c + 4 * S : c - 4 * S, er, ei);
+                accR[S - 1] = er;
+                accI[S - 1] = ei;
+            }
+            __syncthreads();
+            // ---- every wave: its four rows of the solved block to memory
+            // (forward: times D^-1), then pending tiles -= Q_jc x_c
+            {
+                const int rl = 4 * w + g, row = TB * c + rl;
+                T vr = YR[par][rl][n], vi = YI[par][rl][n];
+                if (FWD) {
+                    const cplx<T> o = cmul(cplx<T>{vr, vi}, cinv_fast(dx));
+                    vr = o.re;
+                    vi = o.im;
+                }
+                if (nlive && row < Mx) {
+                    vout_re[row] = vr;
+                    vout_im[row] = vi;
+                }
+            }
+            const int delta = FWD ? ((w - c - 1) & 3) + 1 : ((c - w - 1) & 3) + 1;
+            T br[4], bi[4];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                br[kk] = YR[par][4 * kk + g][n];
+                bi[kk] = YI[par][4 * kk + g][n];
+            }
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+                const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
+                if (couples(j, c)) {
+                    // masks only where some entry can fall outside: the
+                    // last tile of the band, the last (ragged) column block
+                    const bool edge = (FWD ? j - c : c - j) == NB || (FWD ? c : j) == nblk - 1;
+                    if (edge) {
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk) {
+                            const bool on = q_on(j, c, kk);
+                            qx[t][kk].re = on ? qx[t][kk].re : T(0);
+                            qx[t][kk].im = on ? qx[t][kk].im : T(0);
+                        }
+                    }
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        const cplx<T> a = qx[t][kk];
+                        accR[t] = mfma16x16x4<T>(-a.re, br[kk], accR[t]);
+                        accR[t] = mfma16x16x4<T>(a.im, bi[kk], accR[t]);
+                        accI[t] = mfma16x16x4<T>(-a.re, bi[kk], accI[t]);
+                        accI[t] = mfma16x16x4<T>(-a.im, br[kk], accI[t]);
+                    }
+                }
+            }
+        }
+        fetch(s + NSET, qx, px, dx, ex);
+    };
+
+    for (int s0 = 0; s0 < nblk; s0 += NSET) {
+#pragma unroll
+        for (int u = 0; u < NSET; ++u) step(s0 + u, qa[u], pa[u], da[u], ea[u]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_band_diag_inverse(const void* LB, void* LI, int Mx, int bp, int nsys, hipStream_t st) {
+    const int nblk = (Mx + TB - 1) / TB;
+    const long long nb = (long long)nsys * nblk;
+    const long long grid = (nb + 7) / 8;
+    hipLaunchKernelGGL(band_diag_inverse_kernel<T>, dim3((unsigned)grid), dim3(128), 0, st,
+                       static_cast<const cplx<T>*>(LB), static_cast<cplx<T>*>(LI), Mx, bp, nblk, nb);
+    return hipGetLastError();
+}
+
+template <typename T, bool FWD, int S>
+static hipError_t launch_tile_t(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
+                                const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun) {
+    constexpr int NSET = sizeof(T) == 4 ? 3 : 2;     // prefetch distance in steps
+    dim3 grid(nrun, (nrhs + TB - 1) / TB);
+    hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET>), grid, dim3(256), 0, st,
+                       static_cast<const cplx<T>*>(LB), static_cast<const cplx<T>*>(LI), Mx, bp, nsys, nrhs,
+                       static_cast<const T*>(Vin), static_cast<T*>(Vout), sys0, reach, launch_gate());
+    return hipGetLastError();
+}
+
+template <typename T, bool FWD>
+static hipError_t launch_tile(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
+                              const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun) {
+    if (bp < TB || bp % TB != 0 || bp > TILE_BPMAX || sys0 < 0 || nrun < 1 || sys0 + nrun > nsys || nrhs < 1)
+        return hipErrorInvalidValue;
+    const int slots = (bp / TB + 3) / 4;
+    switch (slots) {
+        case 1: return launch_tile_t<T, FWD, 1>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
+        case 2: return launch_tile_t<T, FWD, 2>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
+        case 3: return launch_tile_t<T, FWD, 3>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
+        default: return launch_tile_t<T, FWD, 4>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
+    }
+}
+
+template <typename T>
+hipError_t launch_tile_forward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
+                               const void* G, void* W, hipStream_t st, int sys0, int nrun) {
+    return launch_tile<T, true>(LB, LI, reach, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+}
+
+template <typename T>
+hipError_t launch_tile_backward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
+                                void* W, hipStream_t st, int sys0, int nrun) {
+    return launch_tile<T, false>(LB, LI, reach, Mx, bp, nsys, nrhs, W, W, st, sys0, nrun);
+}
+
+template hipError_t launch_band_diag_inverse<float>(const void*, void*, int, int, int, hipStream_t);
+template hipError_t launch_band_diag_inverse<double>(const void*, void*, int, int, int, hipStream_t);
+template hipError_t launch_tile_forward<float>(const void*, const void*, const int*, int, int, int, int, const void*,
+                                               void*, hipStream_t, int, int);
+template hipError_t launch_tile_forward<double>(const void*, const void*, const int*, int, int, int, int, const void*,
+                                                void*, hipStream_t, int, int);
+template hipError_t launch_tile_backward<float>(const void*, const void*, const int*, int, int, int, int, void*,
+                                                hipStream_t, int, int);
+template hipError_t launch_tile_backward<double>(const void*, const void*, const int*, int, int, int, int, void*,
+                                                 hipStream_t, int, int);
+
+}  // namespace stfd

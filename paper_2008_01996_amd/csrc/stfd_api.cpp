@@ -14,58 +14,17 @@
 #include "host_internal.hpp"
 #include "host_linalg.hpp"
 #include "kernels.hpp"
+#include "problem.hpp"
 
 using stfd::cd;
 using stfd::fail;
 
-struct stfd_problem {
-    const stfd_space* space = nullptr;
-    stfd_opts opts{};
-    int Nt = 0, Mx = 0, b = 0, bp = 0, nsys = 0, npair = 0, nreal = 0;
-    int method = STFD_METHOD_FD;
-    stfd_setup_report rep{};
-    std::vector<double> lam_sys;   // 2 nsys (re, im)
-    bool factored = false;
-    // device data
-    int* d_rowptr = nullptr;
-    int* d_col = nullptr;
-    double* d_valM = nullptr;
-    double* d_valA = nullptr;
-    double* d_lam = nullptr;
-    double* d_W1 = nullptr;     // Nt x 2Nt  FP64: [Re | Im] of A_t^-1 conj(U_t) Sigma^-1
-    float* d_W1f = nullptr;     // FP32 copy (first forward GEMM in FP32)
-    void* d_W2 = nullptr;       // 2Nt x 2nsys  [[Re, Im], [-Im, Re]] of V_t^T[:, sys], working precision
-    void* d_Xb = nullptr;       // 2nsys x Nt   [Re; -Im] of c_k x_k^T, working precision
-    double* d_W2d = nullptr;    // FP64 copies for FP64 transforms in the FP32 form
-    double* d_Xbd = nullptr;
-    double* d_Bres = nullptr;   // 2Nt x Nt     [A_t^T; M_t^T]
-    double* d_S = nullptr;      // Alg. BSc: Nt x Nt upper-triangular Schur factor, complex interleaved
-    void* d_LB = nullptr;       // band factors
-    int* d_flag = nullptr;
-    // work buffers, sized for nrhs_cap right-hand sides
-    int nrhs_cap = 0;
-    void* d_T1 = nullptr;       // Mx x 2Nt per RHS (FP32 or FP64)
-    void* d_G = nullptr;        // Mx x 2nsys per RHS
-    double* d_P = nullptr;      // Mx x 2Nt per RHS
-    double* d_R = nullptr;      // Mx x Nt per RHS
-    double* d_part = nullptr;
-    double* d_norms = nullptr;
-    // per-stage event timing
-    struct ProfRec {
-        int stage;
-        hipEvent_t a, b;
-    };
-    bool prof_on = false;
-    std::vector<hipEvent_t> ev_pool;    // all events ever created
-    size_t ev_used = 0;                 // events handed out since the last drain
-    std::vector<ProfRec> prof_recs;
-    double prof_ms[STFD_NSTAGE] = {};
-    long long prof_cnt[STFD_NSTAGE] = {};
-};
 
 namespace {
 
 bool is_fp32(const stfd_problem* p) { return p->opts.precision == STFD_PREC_FP32; }
+void drop_graphs(stfd_problem* p);
+int ensure_ctl(stfd_problem* p);
 
 int hip_fail(hipError_t e, const char* what) {
     return fail(STFD_EHIP, std::string(what) + ": " + hipGetErrorString(e));
@@ -91,11 +50,12 @@ int upload(T** dst, const void* src, size_t bytes, hipStream_t st) {
 void free_work(stfd_problem* p) {
     (void)hipFree(p->d_T1);
     (void)hipFree(p->d_G);
+    (void)hipFree(p->d_Gs);
     (void)hipFree(p->d_P);
     (void)hipFree(p->d_R);
     (void)hipFree(p->d_part);
     (void)hipFree(p->d_norms);
-    p->d_T1 = p->d_G = nullptr;
+    p->d_T1 = p->d_G = p->d_Gs = nullptr;
     p->d_P = p->d_R = p->d_part = p->d_norms = nullptr;
     p->nrhs_cap = 0;
 }
@@ -173,15 +133,43 @@ int decompose(int n, const double* At, const double* Mt, Decomp& D) {
     if (!stfd::eig_real(n, C, vals, vecs, &err)) return fail(STFD_ENUMERIC, err);
     // x = L^-T y
     stfd::chol_backward(n, D.L, vecs.data(), n);
+    // real or one of a conjugate pair.  The complex QR perturbs every
+    // eigenvalue by about eps ||C|| cond(lambda), an absolute amount set by
+    // the largest eigenvalues, so a real eigenvalue (however small) comes
+    // out with an imaginary part of that size: the threshold is relative to
+    // max |lambda|.  Every eigenvalue above the real axis must then find its
+    // conjugate below it (computed separately, the two differ by up to about
+    // 1e-8 max |lambda| on the graded N_t = 1024 mesh; 1e-6 max |lambda| is
+    // allowed, far below the spacing of distinct eigenvalues).  A genuine pair whose
+    // imaginary part hid below the threshold would be taken as two real
+    // eigenvalues with the real parts of complex eigenvectors; the eigen
+    // residual check below refuses that.
     double lmax = 0.0;
     for (auto& v : vals) lmax = std::max(lmax, std::abs(v));
     const double tol = 1e-9 * std::max(lmax, 1e-300);
-    std::vector<int> up, re;
-    int ndown = 0;
+    std::vector<int> up, re, down;
     for (int k = 0; k < n; ++k) {
         if (vals[k].imag() > tol) up.push_back(k);
-        else if (vals[k].imag() < -tol) ++ndown;
+        else if (vals[k].imag() < -tol) down.push_back(k);
         else re.push_back(k);
+    }
+    const int ndown = (int)down.size();
+    if ((int)up.size() == ndown) {
+        std::vector<char> used(down.size(), 0);
+        for (int k : up) {
+            int best = -1;
+            double bd = 0.0;
+            for (size_t q = 0; q < down.size(); ++q) {
+                if (used[q]) continue;
+                const double d = std::abs(vals[down[q]] - std::conj(vals[k]));
+                if (best < 0 || d < bd) {
+                    best = (int)q;
+                    bd = d;
+                }
+            }
+            if (bd > 1e-6 * lmax) return fail(STFD_ENUMERIC, "eigenvalues do not pair into conjugates");
+            used[best] = 1;
+        }
     }
     if ((int)up.size() != ndown) return fail(STFD_ENUMERIC, "eigenvalues do not pair into conjugates");
     D.npair = (int)up.size();
@@ -224,6 +212,8 @@ int decompose(int n, const double* At, const double* Mt, Decomp& D) {
     }
     // eigen residual  ||M x - lam A x|| / ((||M|| + |lam| ||A||) ||x||)
     D.eig_res = stfd::eig_residual(n, At, Mt, D.lam, D.X);
+    if (!(D.eig_res <= 1e-10))
+        return fail(STFD_ENUMERIC, "eigen residual of the time pencil " + std::to_string(D.eig_res) + " above 1e-10");
     for (auto& l : D.lam)
         if (!(l.real() > 0.0)) return fail(STFD_ENUMERIC, "an eigenvalue of (M_t, A_t) has Re <= 0");
     std::vector<cd> Xw = D.X;
@@ -250,6 +240,7 @@ void fill_report(const Decomp& D, stfd_setup_report* r) {
 
 int ensure_work(stfd_problem* p, int nrhs) {
     if (nrhs <= p->nrhs_cap) return STFD_OK;
+    drop_graphs(p);                     // captured rounds refer to the old buffers
     free_work(p);
     const size_t Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
     const size_t es = is_fp32(p) ? 4 : 8;
@@ -257,6 +248,7 @@ int ensure_work(stfd_problem* p, int nrhs) {
     struct { void** ptr; size_t bytes; } req[] = {
         {&p->d_T1, Mx * 2 * Nt * es * nrhs},
         {&p->d_G, Mx * 2 * ns * es * nrhs},
+        {&p->d_Gs, p->opts.inner_refine > 0 ? Mx * 2 * ns * es * nrhs : 0},
         {reinterpret_cast<void**>(&p->d_P), Mx * 2 * Nt * 8 * nrhs},
         {reinterpret_cast<void**>(&p->d_R), Mx * Nt * 8 * nrhs},
         {reinterpret_cast<void**>(&p->d_part), parts * 2 * 8},
@@ -271,6 +263,56 @@ int ensure_work(stfd_problem* p, int nrhs) {
     }
     p->nrhs_cap = nrhs;
     return STFD_OK;
+}
+
+// band factors and, with the tile sweeps, the inverses of their diagonal blocks
+int ensure_factor_storage(stfd_problem* p) {
+    const size_t es = is_fp32(p) ? 8 : 16;
+    if (!p->d_LB) {
+        hipError_t e = hipMalloc(&p->d_LB, (size_t)p->nsys * p->Mx * (p->bp + 1) * es);
+        if (e != hipSuccess) {
+            p->d_LB = nullptr;
+            return fail(STFD_ENOMEM, std::string("band factor storage: ") + hipGetErrorString(e));
+        }
+    }
+    if (p->tile_min_rhs > 0 && p->bp <= stfd::TILE_BPMAX && !p->d_LI) {
+        const size_t nblk = ((size_t)p->Mx + 15) / 16;
+        hipError_t e = hipMalloc(&p->d_LI, (size_t)p->nsys * nblk * 256 * es);
+        if (e != hipSuccess) {
+            p->d_LI = nullptr;
+            return fail(STFD_ENOMEM, std::string("diagonal block inverses: ") + hipGetErrorString(e));
+        }
+    }
+    return STFD_OK;
+}
+
+// with opts.nrhs_max > 0: everything factor and solve need, allocated at setup
+int preallocate(stfd_problem* p) {
+    if (p->opts.nrhs_max <= 0) return STFD_OK;
+    int rc = ensure_factor_storage(p);
+    if (!rc) rc = ensure_work(p, p->opts.nrhs_max);
+    if (!rc) rc = ensure_ctl(p);
+    return rc;
+}
+
+// device control of the refinement (captured rounds) and its pinned host mirror
+int ensure_ctl(stfd_problem* p) {
+    if (p->d_ctl) return STFD_OK;
+    hipError_t e = hipMalloc(&p->d_ctl, 4 * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc(&p->d_hist, STFD_MAX_HIST * sizeof(double));
+    if (e == hipSuccess) e = hipHostMalloc(&p->h_ctl, 4 * sizeof(int));
+    if (e == hipSuccess) e = hipHostMalloc(&p->h_hist, STFD_MAX_HIST * sizeof(double));
+    if (e != hipSuccess) return fail(STFD_ENOMEM, std::string("refinement control: ") + hipGetErrorString(e));
+    return STFD_OK;
+}
+
+void drop_graphs(stfd_problem* p) {
+    if (p->g_first) (void)hipGraphExecDestroy(p->g_first);
+    if (p->g_next) (void)hipGraphExecDestroy(p->g_next);
+    p->g_first = p->g_next = nullptr;
+    p->g_F = nullptr;
+    p->g_U = nullptr;
+    p->g_nrhs = 0;
 }
 
 }  // namespace
@@ -433,6 +475,7 @@ int bs_setup(const stfd_space* space, int n, const double* At, const double* Mt,
     int zero = 0, e = 0;
     if ((e = upload(&p->d_rowptr, s->rowptr.data(), s->rowptr.size() * sizeof(int), st)) ||
         (e = upload(&p->d_col, s->col.data(), s->col.size() * sizeof(int), st)) ||
+        (e = upload(&p->d_reach, s->block_reach.data(), s->block_reach.size() * sizeof(int), st)) ||
         (e = upload(&p->d_valM, s->valM.data(), s->valM.size() * sizeof(double), st)) ||
         (e = upload(&p->d_valA, s->valA.data(), s->valA.size() * sizeof(double), st)) ||
         (e = upload(&p->d_lam, p->lam_sys.data(), p->lam_sys.size() * sizeof(double), st)) ||
@@ -451,6 +494,13 @@ int bs_setup(const stfd_space* space, int n, const double* At, const double* Mt,
     }
     p->rep.factor_bytes = (double)n * p->Mx * (p->bp + 1) * 16;
     p->rep.setup_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    {
+        const int rc2 = preallocate(p);
+        if (rc2) {
+            stfd_problem_free(p);
+            return rc2;
+        }
+    }
     *out = p;
     stfd::clear_error();
     return STFD_OK;
@@ -482,8 +532,18 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     if (opts) o = *opts;
     if ((o.precision != STFD_PREC_FP32 && o.precision != STFD_PREC_FP64) || !(o.rtol >= 0.0) || o.max_refine < 0 ||
         o.max_refine >= STFD_MAX_HIST || o.fp64_transforms < 0 || o.fp64_transforms > 7 ||
-        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC))
+        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC) || o.inner_refine < 0 || o.inner_refine > 1 ||
+        o.graph < 0 || o.graph > 1 || o.nrhs_max < 0)
         return fail(STFD_EINVAL, "fd_setup: bad options");
+    {
+        const int bp = std::max(16, (space->half_band + 15) / 16 * 16);
+        if (bp > stfd::BAND_BPMAX)
+            return fail(STFD_EINVAL, "fd_setup: padded half-bandwidth " + std::to_string(bp) +
+                                         " of the spatial matrices exceeds " + std::to_string(stfd::BAND_BPMAX) +
+                                         ", the largest the substitution sweeps take");
+    }
+    if (o.method == STFD_METHOD_BSC && o.inner_refine != 0)
+        return fail(STFD_EINVAL, "fd_setup: the inner refinement belongs to Algorithm FD");
     if (o.method == STFD_METHOD_BSC) return bs_setup(space, Nt, At, Mt, o, static_cast<hipStream_t>(hip_stream), out);
     const auto t0 = std::chrono::steady_clock::now();
     Decomp D;
@@ -517,6 +577,10 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     std::vector<int> sys(ns);
     for (int q = 0; q < D.npair; ++q) sys[q] = q;
     for (int q = 0; q < D.nreal; ++q) sys[D.npair + q] = 2 * D.npair + q;
+    // tile sweeps from 8 right-hand sides on, where they measured faster
+    // than the lane-chain sweeps for every workload shape (the autotuner
+    // refines this per shape)
+    p->tile_min_rhs = p->bp <= stfd::TILE_BPMAX ? 8 : 0;
     p->lam_sys.resize(2 * ns);
     for (int q = 0; q < ns; ++q) {
         p->lam_sys[2 * q] = D.lam[sys[q]].real();
@@ -572,6 +636,7 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     int e = 0;
     if ((e = upload(&p->d_rowptr, s->rowptr.data(), s->rowptr.size() * sizeof(int), st)) ||
         (e = upload(&p->d_col, s->col.data(), s->col.size() * sizeof(int), st)) ||
+        (e = upload(&p->d_reach, s->block_reach.data(), s->block_reach.size() * sizeof(int), st)) ||
         (e = upload(&p->d_valM, s->valM.data(), s->valM.size() * sizeof(double), st)) ||
         (e = upload(&p->d_valA, s->valA.data(), s->valA.size() * sizeof(double), st)) ||
         (e = upload(&p->d_lam, p->lam_sys.data(), p->lam_sys.size() * sizeof(double), st)) ||
@@ -613,6 +678,13 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     p->rep.factor_bytes = (double)ns * p->Mx * (p->bp + 1) * es;
     p->rep.setup_seconds =
         std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    {
+        const int rc2 = preallocate(p);
+        if (rc2) {
+            stfd_problem_free(p);
+            return rc2;
+        }
+    }
     *out = p;
     stfd::clear_error();
     return STFD_OK;
@@ -624,19 +696,47 @@ extern "C" int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* re
     return STFD_OK;
 }
 
+extern "C" int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t) {
+    if (!p || !t) return fail(STFD_EINVAL, "get_tuning: bad arguments");
+    t->sweep_tile_min_rhs = p->tile_min_rhs;
+    t->gemm_tile_m_fp32 = p->gemm_bm[0];
+    t->gemm_tile_m_fp64 = p->gemm_bm[1];
+    t->gemm_n_fast = p->gemm_nfast;
+    t->factor_kernel = p->factor_kernel;
+    t->factor_pack_real = p->factor_pack_real;
+    return STFD_OK;
+}
+
+extern "C" int stfd_set_tuning(stfd_problem* p, const stfd_tuning* t) {
+    auto tile_ok = [](int m) { return m == 64 || m == 128; };
+    if (!p || !t || t->sweep_tile_min_rhs < 0 || !tile_ok(t->gemm_tile_m_fp32) || !tile_ok(t->gemm_tile_m_fp64) ||
+        (t->gemm_n_fast != 0 && t->gemm_n_fast != 1) || t->factor_kernel < 0 || t->factor_kernel > 2 ||
+        (t->factor_pack_real != 0 && t->factor_pack_real != 1))
+        return fail(STFD_EINVAL, "set_tuning: bad arguments");
+    drop_graphs(p);                     // captured rounds hold the old kernel choice
+    p->gemm_bm[0] = t->gemm_tile_m_fp32;
+    p->gemm_bm[1] = t->gemm_tile_m_fp64;
+    p->gemm_nfast = t->gemm_n_fast;
+    p->factor_kernel = t->factor_kernel;
+    p->factor_pack_real = t->factor_pack_real;
+    p->tile_min_rhs = p->bp <= stfd::TILE_BPMAX ? t->sweep_tile_min_rhs : 0;
+    if (p->tile_min_rhs == 0) {
+        (void)hipFree(p->d_LI);
+        p->d_LI = nullptr;
+    }
+    p->factored = p->factored && (p->tile_min_rhs == 0 || p->d_LI != nullptr);
+    stfd::clear_error();
+    return STFD_OK;
+}
+
 extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
     if (!p) return fail(STFD_EINVAL, "fd_factor: null problem");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const bool f32 = is_fp32(p);
-    if (!p->d_LB) {
-        const size_t bytes = (size_t)p->nsys * p->Mx * (p->bp + 1) * (f32 ? 8 : 16);
-        hipError_t e = hipMalloc(&p->d_LB, bytes);
-        if (e != hipSuccess) {
-            p->d_LB = nullptr;
-            return fail(STFD_ENOMEM, std::string("band factor storage: ") + hipGetErrorString(e));
-        }
-    }
-    HIPCHK(hipMemsetAsync(p->d_flag, 0, sizeof(int), st), "fd_factor: clear flag");
+    int rc = ensure_factor_storage(p);
+    if (rc) return rc;
+    const bool tiles = p->d_LI != nullptr;
+    HIPCHK(stfd::launch_reset_ints(p->d_flag, 1, st), "fd_factor: clear flag");
     {
         StageTimer tm(p, STFD_ST_BAND_INIT, st);
         HIPCHK(f32 ? stfd::launch_band_init<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_rowptr, p->d_col,
@@ -647,9 +747,20 @@ extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
     }
     {
         StageTimer tm(p, STFD_ST_BAND_LDL, st);
-        HIPCHK(f32 ? stfd::launch_band_ldl<float>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st)
-                   : stfd::launch_band_ldl<double>(p->d_LB, p->Mx, p->bp, p->nsys, p->d_flag, st),
+        // FD orders its systems [pairs | real], the real ones with lambda
+        // exactly real; BSc's Schur diagonal has no such order
+        const int nreal = p->method == STFD_METHOD_FD && p->factor_pack_real ? p->nreal : 0;
+        HIPCHK(f32 ? stfd::launch_band_ldl<float>(p->d_LB, p->Mx, p->bp, p->nsys, nreal, p->d_reach, p->d_flag,
+                                                  p->factor_kernel, st)
+                   : stfd::launch_band_ldl<double>(p->d_LB, p->Mx, p->bp, p->nsys, nreal, p->d_reach, p->d_flag,
+                                                   p->factor_kernel, st),
                "band LDL^T");
+    }
+    if (tiles) {
+        StageTimer tm(p, STFD_ST_BAND_LDL, st);
+        HIPCHK(f32 ? stfd::launch_band_diag_inverse<float>(p->d_LB, p->d_LI, p->Mx, p->bp, p->nsys, st)
+                   : stfd::launch_band_diag_inverse<double>(p->d_LB, p->d_LI, p->Mx, p->bp, p->nsys, st),
+               "diagonal block inverses");
     }
     p->factored = true;
     stfd::clear_error();
@@ -660,6 +771,25 @@ namespace {
 
 int spatial_sweeps(stfd_problem* p, int nrhs, const void* G, void* Z, hipStream_t st) {
     const bool f32 = is_fp32(p);
+    if (p->d_LI && nrhs >= p->tile_min_rhs) {
+        {
+            StageTimer tm(p, STFD_ST_SWEEP_FWD, st);
+            HIPCHK(f32 ? stfd::launch_tile_forward<float>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0,
+                                                          p->nsys)
+                       : stfd::launch_tile_forward<double>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0,
+                                                           p->nsys),
+                   "forward tile sweep");
+        }
+        {
+            StageTimer tm(p, STFD_ST_SWEEP_BWD, st);
+            HIPCHK(f32 ? stfd::launch_tile_backward<float>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, Z, st, 0,
+                                                           p->nsys)
+                       : stfd::launch_tile_backward<double>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, Z, st, 0,
+                                                            p->nsys),
+                   "backward tile sweep");
+        }
+        return STFD_OK;
+    }
     {
         StageTimer tm(p, STFD_ST_SWEEP_FWD, st);
         HIPCHK(f32 ? stfd::launch_band_forward<float>(p->d_LB, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0, p->nsys)
@@ -673,6 +803,16 @@ int spatial_sweeps(stfd_problem* p, int nrhs, const void* G, void* Z, hipStream_
                "backward sweep");
     }
     return STFD_OK;
+}
+
+// the problem's GEMM variant for this kind (tile height by the precision of
+// its matrix cores, grid order)
+hipError_t launch_gemm_tuned(const stfd_problem* p, stfd::GemmKind kind, const stfd::GemmArgs& g0, hipStream_t st) {
+    stfd::GemmArgs g = g0;
+    const bool mfma32 = kind == stfd::GEMM_D_F_STORE_F || kind == stfd::GEMM_F_F_STORE_F || kind == stfd::GEMM_F_F_ADD_D;
+    g.bm = p->gemm_bm[mfma32 ? 0 : 1];
+    g.nfast = p->gemm_nfast;
+    return stfd::launch_gemm(kind, g, st);
 }
 
 // one FD application: X (FP64 residual or load, Mx x Nt per RHS) -> U += alpha FD(X)
@@ -692,25 +832,48 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     stfd::GemmKind k1 = !f32 ? stfd::GEMM_D_D_STORE_D : ((mask & 1) ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_F_STORE_F);
     {
         StageTimer tm(p, STFD_ST_FWD1, st);
-        HIPCHK(stfd::launch_gemm(k1, g, st), "forward transform 1");
+        HIPCHK(launch_gemm_tuned(p, k1, g, st), "forward transform 1");
     }
     // step 2b: G = T1 W2   (Mx x 2nsys)
     g = stfd::GemmArgs{};
-    g.A = p->d_T1; g.B = (f32 && (mask & 2)) ? static_cast<const void*>(p->d_W2d) : p->d_W2; g.C = p->d_G;
+    const bool inner = p->opts.inner_refine > 0;
+    g.A = p->d_T1; g.B = (f32 && (mask & 2)) ? static_cast<const void*>(p->d_W2d) : p->d_W2;
+    g.C = inner ? p->d_Gs : p->d_G;
     g.M = Mx; g.N = 2 * ns; g.K = 2 * Nt;
     g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * 2 * ns;
     g.batch = nrhs;
     {
         StageTimer tm(p, STFD_ST_FWD2, st);
-        HIPCHK(stfd::launch_gemm(!f32 ? stfd::GEMM_D_D_STORE_D
+        HIPCHK(launch_gemm_tuned(p, !f32 ? stfd::GEMM_D_D_STORE_D
                                        : ((mask & 2) ? stfd::GEMM_F_D_STORE_F : stfd::GEMM_F_F_STORE_F),
                                  g, st),
                "forward transform 2");
     }
-    // step 3: spatial solves, in place in G
-    int rc = spatial_sweeps(p, nrhs, p->d_G, p->d_G, st);
+    // step 3: spatial solves, in place in G (with the inner refinement: G
+    // kept in Gs, Z into G; then Gs -= S_k Z in FP64, solved in place, and
+    // the correction added to Z)
+    int rc = spatial_sweeps(p, nrhs, inner ? p->d_Gs : p->d_G, p->d_G, st);
     if (rc) return rc;
+    if (inner) {
+        {
+            StageTimer tm(p, STFD_ST_INNER, st);
+            HIPCHK(f32 ? stfd::launch_spatial_resid<float>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA,
+                                                           p->d_lam, p->d_Gs, p->d_G, st)
+                       : stfd::launch_spatial_resid<double>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM,
+                                                            p->d_valA, p->d_lam, p->d_Gs, p->d_G, st),
+                   "inner residual");
+        }
+        rc = spatial_sweeps(p, nrhs, p->d_Gs, p->d_Gs, st);
+        if (rc) return rc;
+        {
+            StageTimer tm(p, STFD_ST_INNER, st);
+            const size_t n = (size_t)Mx * 2 * ns * nrhs;
+            HIPCHK(f32 ? stfd::launch_add<float>(p->d_G, p->d_Gs, n, st)
+                       : stfd::launch_add<double>(p->d_G, p->d_Gs, n, st),
+                   "inner update");
+        }
+    }
     // step 4: U += Re(Z Xb)
     g = stfd::GemmArgs{};
     g.A = p->d_G; g.B = (f32 && (mask & 4)) ? static_cast<const void*>(p->d_Xbd) : p->d_Xb; g.C = U;
@@ -720,7 +883,7 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     g.batch = nrhs; g.alpha = 1.0;
     {
         StageTimer tm(p, STFD_ST_BACK, st);
-        HIPCHK(stfd::launch_gemm(!f32 ? stfd::GEMM_D_D_ADD_D
+        HIPCHK(launch_gemm_tuned(p, !f32 ? stfd::GEMM_D_D_ADD_D
                                        : ((mask & 4) ? stfd::GEMM_F_D_ADD_D : stfd::GEMM_F_F_ADD_D),
                                  g, st),
                "back transform");
@@ -740,7 +903,7 @@ int bs_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     g.batch = nrhs;
     {
         StageTimer tm(p, STFD_ST_FWD1, st);
-        HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_STORE_D, g, st), "BSc forward transform");
+        HIPCHK(launch_gemm_tuned(p, stfd::GEMM_D_D_STORE_D, g, st), "BSc forward transform");
     }
     // step 3: systems k = n-1 .. 0 one after the other; each solved z_k is
     // coupled into the right-hand sides of the systems before it
@@ -771,7 +934,7 @@ int bs_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     g.batch = nrhs; g.alpha = 1.0;
     {
         StageTimer tm(p, STFD_ST_BACK, st);
-        HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_ADD_D, g, st), "BSc back transform");
+        HIPCHK(launch_gemm_tuned(p, stfd::GEMM_D_D_ADD_D, g, st), "BSc back transform");
     }
     return STFD_OK;
 }
@@ -798,7 +961,7 @@ int residual(stfd_problem* p, int nrhs, const double* F, const double* U, double
     g.batch = nrhs;
     {
         StageTimer tm(p, STFD_ST_RESID, st);
-        HIPCHK(stfd::launch_gemm(stfd::GEMM_D_D_RESID, g, st), "residual");
+        HIPCHK(launch_gemm_tuned(p, stfd::GEMM_D_D_RESID, g, st), "residual");
     }
     {
         StageTimer tm(p, STFD_ST_REDUCE, st);
@@ -855,10 +1018,124 @@ extern "C" int stfd_system_lambdas(const stfd_problem* p, double* lam) {
     return STFD_OK;
 }
 
+namespace {
+
+// one refinement round: U += FD(X) (or BSc), R = F - K_h U with its norms,
+// then the device-side convergence check
+int refine_round(stfd_problem* p, int nrhs, const double* X, const double* F, double* U, hipStream_t st) {
+    int rc = method_apply(p, nrhs, X, U, st);
+    if (rc) return rc;
+    rc = residual(p, nrhs, F, U, p->d_R, st);
+    if (rc) return rc;
+    HIPCHK(stfd::launch_refine_check(p->d_norms, nrhs, p->opts.rtol, p->d_flag, p->opts.max_refine + 1, p->d_ctl,
+                                     p->d_hist, st),
+           "refinement check");
+    return STFD_OK;
+}
+
+// records the launches of fn (on stream cs) as a graph and instantiates it;
+// the kernels are gated on gate
+template <typename Fn>
+int capture(hipStream_t cs, const int* gate, hipGraphExec_t* out, Fn fn) {
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed), "begin capture");
+    stfd::set_launch_gate(gate);
+    const int rc = fn();
+    stfd::set_launch_gate(nullptr);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+        *out = nullptr;
+        return hip_fail(ei, "graph instantiate");
+    }
+    return STFD_OK;
+}
+
+int capture_rounds(stfd_problem* p, int nrhs, const double* F, double* U) {
+    drop_graphs(p);
+    if (!p->cap_stream) HIPCHK(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking), "capture stream");
+    int rc = capture(p->cap_stream, p->d_ctl, &p->g_first,
+                     [&] { return refine_round(p, nrhs, F, F, U, p->cap_stream); });
+    if (rc) return rc;
+    rc = capture(p->cap_stream, p->d_ctl, &p->g_next,
+                 [&] { return refine_round(p, nrhs, p->d_R, F, U, p->cap_stream); });
+    if (rc) {
+        drop_graphs(p);
+        return rc;
+    }
+    p->g_F = F;
+    p->g_U = U;
+    p->g_nrhs = nrhs;
+    return STFD_OK;
+}
+
+// report and return code from the host mirror of the device control
+int finish_report(stfd_problem* p, int nrhs, std::chrono::steady_clock::time_point t0, stfd_solve_report* rep) {
+    stfd_solve_report r{};
+    r.nrhs = nrhs;
+    r.iterations = p->h_ctl[1];
+    for (int a = 0; a < r.iterations && a < STFD_MAX_HIST; ++a) r.rel_residual[a] = p->h_hist[a];
+    r.converged = p->h_ctl[2] == 1;
+    r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    p->last_apps = r.iterations;
+    if (rep) *rep = r;
+    switch (p->h_ctl[2]) {
+        case 1: stfd::clear_error(); return STFD_OK;
+        case 2: return fail(STFD_ENUMERIC, "fd_solve: zero or non-finite pivot in a band factor");
+        case 4: return fail(STFD_ENUMERIC, "fd_solve: non-finite residual");
+        default: return fail(STFD_ENOCONV, "fd_solve: rtol not reached within max_refine");
+    }
+}
+
+// the refined solve as captured rounds: the first rounds are launched ahead
+// (as many as the last solve needed), then one host synchronisation reads
+// the device control; more rounds follow one at a time only if needed
+int solve_graph(stfd_problem* p, int nrhs, const double* F, double* U, stfd_solve_report* rep, hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    int rc = ensure_work(p, nrhs);
+    if (rc) return rc;
+    rc = ensure_ctl(p);
+    if (rc) return rc;
+    if (!p->g_first || p->g_F != F || p->g_U != U || p->g_nrhs != nrhs) {
+        rc = capture_rounds(p, nrhs, F, U);
+        if (rc) return rc;
+    }
+    HIPCHK(stfd::launch_fill_zero(U, (size_t)p->Mx * p->Nt * nrhs, st), "zero U");
+    HIPCHK(stfd::launch_reset_ints(p->d_ctl, 4, st), "reset control");
+    const int max_apps = p->opts.max_refine + 1;
+    HIPCHK(hipGraphLaunch(p->g_first, st), "graph launch");
+    int launched = 1;
+    const int ahead = std::min(max_apps, std::max(2, p->last_apps));
+    while (launched < ahead) {
+        HIPCHK(hipGraphLaunch(p->g_next, st), "graph launch");
+        ++launched;
+    }
+    for (;;) {
+        HIPCHK(hipMemcpyAsync(p->h_ctl, p->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st), "control copy");
+        HIPCHK(hipMemcpyAsync(p->h_hist, p->d_hist, STFD_MAX_HIST * sizeof(double), hipMemcpyDeviceToHost, st),
+               "history copy");
+        HIPCHK(hipStreamSynchronize(st), "fd_solve: sync");
+        if (p->h_ctl[0] || launched >= max_apps) break;
+        HIPCHK(hipGraphLaunch(p->g_next, st), "graph launch");
+        ++launched;
+    }
+    return finish_report(p, nrhs, t0, rep);
+}
+
+}  // namespace
+
 extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, double* U_dev, stfd_solve_report* rep,
                              void* hip_stream) {
     if (!p || nrhs < 1 || !F_dev || !U_dev) return fail(STFD_EINVAL, "fd_solve: bad arguments");
     if (!p->factored) return fail(STFD_ESTATE, "fd_solve: call stfd_fd_factor first");
+    if (p->opts.graph && !p->prof_on && p->method == STFD_METHOD_FD)
+        return solve_graph(p, nrhs, F_dev, U_dev, rep, static_cast<hipStream_t>(hip_stream));
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     int rc = ensure_work(p, nrhs);
@@ -906,6 +1183,7 @@ extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, dou
         if (rc) return rc;
     }
     r.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    p->last_apps = r.iterations;
     if (rep) *rep = r;
     if (status == STFD_ENUMERIC) return fail(STFD_ENUMERIC, "fd_solve: non-finite residual");
     if (status == STFD_ENOCONV) return fail(STFD_ENOCONV, "fd_solve: rtol not reached within max_refine");
@@ -918,7 +1196,128 @@ extern "C" int stfd_fd_solve(stfd_problem* p, int nrhs, const double* F_dev, dou
 // ---------------------------------------------------------------------------
 struct stfd_batch {
     std::vector<stfd_problem*> probs;
+    // captured rounds of the whole batch: each problem's round on one of
+    // NSIDE forked streams (independent branches of one graph), valid for
+    // the loads, solutions and right-hand-side counts in key_*
+    static constexpr int NSIDE = 4;
+    hipStream_t cap = nullptr;
+    hipStream_t side[NSIDE] = {};
+    hipEvent_t ev_fork = nullptr;
+    hipEvent_t ev_join[NSIDE] = {};
+    hipGraphExec_t g_first = nullptr, g_next = nullptr;
+    std::vector<const double*> key_F;
+    std::vector<double*> key_U;
+    std::vector<int> key_n;
+    int last_apps = 0;
 };
+
+namespace {
+
+void batch_drop_graphs(stfd_batch* b) {
+    if (b->g_first) (void)hipGraphExecDestroy(b->g_first);
+    if (b->g_next) (void)hipGraphExecDestroy(b->g_next);
+    b->g_first = b->g_next = nullptr;
+    b->key_F.clear();
+    b->key_U.clear();
+    b->key_n.clear();
+}
+
+int batch_streams(stfd_batch* b) {
+    if (b->cap) return STFD_OK;
+    HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "batch capture stream");
+    for (int s = 0; s < stfd_batch::NSIDE; ++s) {
+        HIPCHK(hipStreamCreateWithFlags(&b->side[s], hipStreamNonBlocking), "batch side stream");
+        HIPCHK(hipEventCreateWithFlags(&b->ev_join[s], hipEventDisableTiming), "batch event");
+    }
+    HIPCHK(hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming), "batch event");
+    return STFD_OK;
+}
+
+// one round of every problem, problem i on side stream i mod NSIDE, forked
+// from and joined back into the capture stream (X = F on the first round,
+// the residual after it)
+int batch_round(stfd_batch* b, bool first, const int* nrhs, const double* const* F, double* const* U) {
+    HIPCHK(hipEventRecord(b->ev_fork, b->cap), "fork");
+    for (int s = 0; s < stfd_batch::NSIDE; ++s) HIPCHK(hipStreamWaitEvent(b->side[s], b->ev_fork, 0), "fork wait");
+    for (size_t i = 0; i < b->probs.size(); ++i) {
+        stfd_problem* p = b->probs[i];
+        stfd::set_launch_gate(p->d_ctl);
+        const int rc = refine_round(p, nrhs[i], first ? F[i] : p->d_R, F[i], U[i], b->side[i % stfd_batch::NSIDE]);
+        if (rc) return rc;
+    }
+    for (int s = 0; s < stfd_batch::NSIDE; ++s) {
+        HIPCHK(hipEventRecord(b->ev_join[s], b->side[s]), "join");
+        HIPCHK(hipStreamWaitEvent(b->cap, b->ev_join[s], 0), "join wait");
+    }
+    return STFD_OK;
+}
+
+int batch_solve_graph(stfd_batch* b, const int* nrhs, const double* const* F, double* const* U,
+                      stfd_solve_report* reps, hipStream_t st) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const int np = (int)b->probs.size();
+    int rc = batch_streams(b);
+    if (rc) return rc;
+    for (int i = 0; i < np; ++i) {
+        stfd_problem* p = b->probs[i];
+        if ((rc = ensure_work(p, nrhs[i])) || (rc = ensure_ctl(p))) return rc;
+    }
+    bool same = b->g_first && (int)b->key_F.size() == np;
+    for (int i = 0; same && i < np; ++i) same = b->key_F[i] == F[i] && b->key_U[i] == U[i] && b->key_n[i] == nrhs[i];
+    if (!same) {
+        batch_drop_graphs(b);
+        rc = capture(b->cap, nullptr, &b->g_first, [&] { return batch_round(b, true, nrhs, F, U); });
+        if (!rc) rc = capture(b->cap, nullptr, &b->g_next, [&] { return batch_round(b, false, nrhs, F, U); });
+        if (rc) {
+            batch_drop_graphs(b);
+            return rc;
+        }
+        b->key_F.assign(F, F + np);
+        b->key_U.assign(U, U + np);
+        b->key_n.assign(nrhs, nrhs + np);
+    }
+    int max_apps = 1;
+    for (int i = 0; i < np; ++i) {
+        stfd_problem* p = b->probs[i];
+        max_apps = std::max(max_apps, p->opts.max_refine + 1);
+        HIPCHK(stfd::launch_fill_zero(U[i], (size_t)p->Mx * p->Nt * nrhs[i], st), "batch: zero U");
+        HIPCHK(stfd::launch_reset_ints(p->d_ctl, 4, st), "batch: reset control");
+    }
+    HIPCHK(hipGraphLaunch(b->g_first, st), "batch graph launch");
+    int launched = 1;
+    const int ahead = std::min(max_apps, std::max(2, b->last_apps));
+    while (launched < ahead) {
+        HIPCHK(hipGraphLaunch(b->g_next, st), "batch graph launch");
+        ++launched;
+    }
+    for (;;) {
+        for (int i = 0; i < np; ++i) {
+            stfd_problem* p = b->probs[i];
+            HIPCHK(hipMemcpyAsync(p->h_ctl, p->d_ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st), "control copy");
+            HIPCHK(hipMemcpyAsync(p->h_hist, p->d_hist, STFD_MAX_HIST * sizeof(double), hipMemcpyDeviceToHost, st),
+                   "history copy");
+        }
+        HIPCHK(hipStreamSynchronize(st), "batch_solve: sync");
+        bool all = true;
+        for (int i = 0; i < np; ++i) all = all && b->probs[i]->h_ctl[0];
+        if (all || launched >= max_apps) break;
+        HIPCHK(hipGraphLaunch(b->g_next, st), "batch graph launch");
+        ++launched;
+    }
+    int first = STFD_OK, most = 0;
+    for (int i = 0; i < np; ++i) {
+        const int r = finish_report(b->probs[i], nrhs[i], t0, reps ? &reps[i] : nullptr);
+        if (first == STFD_OK && r != STFD_OK) first = r;
+        most = std::max(most, b->probs[i]->h_ctl[1]);
+    }
+    b->last_apps = most;
+    if (first == STFD_ENUMERIC) return fail(STFD_ENUMERIC, "batch_solve: zero/non-finite pivot or residual");
+    if (first == STFD_ENOCONV) return fail(STFD_ENOCONV, "batch_solve: rtol not reached within max_refine");
+    stfd::clear_error();
+    return STFD_OK;
+}
+
+}  // namespace
 
 extern "C" int stfd_batch_create(int np, stfd_problem* const* problems, stfd_batch** out) {
     if (!out || np < 1 || !problems) return fail(STFD_EINVAL, "batch_create: bad arguments");
@@ -958,6 +1357,11 @@ extern "C" int stfd_batch_solve(stfd_batch* b, const int* nrhs, const double* co
         if (!p->factored) return fail(STFD_ESTATE, "batch_solve: a problem is not factored");
         const int rc = ensure_work(p, nrhs[i]);
         if (rc) return rc;
+    }
+    {
+        bool graph = true;
+        for (auto* p : b->probs) graph = graph && p->opts.graph && !p->prof_on && p->method == STFD_METHOD_FD;
+        if (graph) return batch_solve_graph(b, nrhs, F_dev, U_dev, reps, st);
     }
     std::vector<stfd_solve_report> r(np);
     std::vector<int> status(np, STFD_ENOCONV), active(np, 1), flag(np, 0);
@@ -1037,7 +1441,17 @@ extern "C" int stfd_batch_solve(stfd_batch* b, const int* nrhs, const double* co
     return STFD_OK;
 }
 
-extern "C" void stfd_batch_free(stfd_batch* b) { delete b; }
+extern "C" void stfd_batch_free(stfd_batch* b) {
+    if (!b) return;
+    batch_drop_graphs(b);
+    for (int s = 0; s < stfd_batch::NSIDE; ++s) {
+        if (b->side[s]) (void)hipStreamDestroy(b->side[s]);
+        if (b->ev_join[s]) (void)hipEventDestroy(b->ev_join[s]);
+    }
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
 
 extern "C" int stfd_profile(stfd_problem* p, int enable) {
     if (!p) return fail(STFD_EINVAL, "profile: null problem");
@@ -1064,10 +1478,17 @@ extern "C" int stfd_profile_read(stfd_problem* p, double* ms, long long* counts)
 
 extern "C" void stfd_problem_free(stfd_problem* p) {
     if (!p) return;
+    drop_graphs(p);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    (void)hipFree(p->d_ctl);
+    (void)hipFree(p->d_hist);
+    (void)hipHostFree(p->h_ctl);
+    (void)hipHostFree(p->h_hist);
     for (auto e : p->ev_pool) (void)hipEventDestroy(e);
     free_work(p);
     (void)hipFree(p->d_rowptr);
     (void)hipFree(p->d_col);
+    (void)hipFree(p->d_reach);
     (void)hipFree(p->d_valM);
     (void)hipFree(p->d_valA);
     (void)hipFree(p->d_lam);
@@ -1080,6 +1501,7 @@ extern "C" void stfd_problem_free(stfd_problem* p) {
     (void)hipFree(p->d_Bres);
     (void)hipFree(p->d_S);
     (void)hipFree(p->d_LB);
+    (void)hipFree(p->d_LI);
     (void)hipFree(p->d_flag);
     delete p;
 }

@@ -31,7 +31,7 @@ EXPORTED = [
 ]
 
 STAGES = ["band_init", "band_ldl", "fwd1", "fwd2", "sweep_fwd", "sweep_bwd", "back", "spatial", "resid",
-          "reduce"]
+          "reduce", "inner"]
 
 
 class StfdError(RuntimeError):
@@ -42,7 +42,16 @@ class StfdError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("fp64_transforms", C.c_int), ("rtol", C.c_double),
-                ("max_refine", C.c_int), ("method", C.c_int)]
+                ("max_refine", C.c_int), ("method", C.c_int), ("inner_refine", C.c_int),
+                ("graph", C.c_int), ("nrhs_max", C.c_int)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("sweep_tile_min_rhs", C.c_int), ("gemm_tile_m_fp32", C.c_int), ("gemm_tile_m_fp64", C.c_int),
+                ("gemm_n_fast", C.c_int), ("factor_kernel", C.c_int), ("factor_pack_real", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class SetupReport(C.Structure):
@@ -100,6 +109,8 @@ def lib():
         L.stfd_fd_setup.argtypes = [vp, C.c_int, dp, dp, C.POINTER(Opts), vp, C.POINTER(vp)]
         L.stfd_fd_setup_report.argtypes = [vp, C.POINTER(SetupReport)]
         L.stfd_fd_factor.argtypes = [vp, vp]
+        L.stfd_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.stfd_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.stfd_fd_solve.argtypes = [vp, C.c_int, vp, vp, C.POINTER(SolveReport), vp]
         L.stfd_kh_residual.argtypes = [vp, C.c_int, vp, vp, vp, dp, vp]
         L.stfd_fd_apply.argtypes = [vp, C.c_int, vp, vp, vp]
@@ -277,11 +288,16 @@ class Problem:
     """Space-time solver (Algorithm FD, or BSc) for one (space, time mesh) pair on the current GPU."""
 
     def __init__(self, space: Space, At, Mt, precision="fp32", fp64_transforms=5, rtol=1e-10, max_refine=30,
-                 stream=None, method="fd"):
+                 stream=None, method="fd", inner_refine=0, graph=True, nrhs_max=0,
+                 tuning="cache"):
         """fp64_transforms (FP32 form only): bit mask of the transform GEMMs run
         on FP64 matrix cores, bit 0 first forward, bit 1 second forward, bit 2
         back transform.  method "fd" (Algorithm FD) or "bsc" (Algorithm BSc,
-        Bartels-Stewart with the complex Schur form; precision "fp64")."""
+        Bartels-Stewart with the complex Schur form; precision "fp64").
+        inner_refine, graph, nrhs_max: the stfd_opts fields of those names.
+        tuning: kernel variants, "cache" (the autotuner's entry for this
+        shape, if any), None (library defaults) or a dict of stfd_tuning
+        fields."""
         self.space = space        # keep alive: the problem refers to it
         At = _f64(At)
         Mt = _f64(Mt)
@@ -294,6 +310,9 @@ class Problem:
         o.rtol = float(rtol)
         o.max_refine = int(max_refine)
         o.method = {"fd": METHOD_FD, "bsc": METHOD_BSC}[method]
+        o.inner_refine = int(inner_refine)
+        o.graph = int(bool(graph))
+        o.nrhs_max = int(nrhs_max)
         self.precision = precision
         self.method = method
         import torch
@@ -305,6 +324,32 @@ class Problem:
         rep = SetupReport()
         _check(lib().stfd_fd_setup_report(self._h, C.byref(rep)))
         self.setup_report = rep.as_dict()
+        # kernel variants: the autotuner's cached choice for this shape
+        # ("cache"), the library defaults (None), or explicit fields (dict)
+        if tuning == "cache":
+            from paper_2008_01996_amd import autotune
+            autotune.apply(self)
+        elif isinstance(tuning, dict):
+            self.set_tuning(**tuning)
+        elif tuning is not None:
+            raise ValueError("tuning: 'cache', None or a dict of stfd_tuning fields")
+
+    def tuning(self):
+        """The kernel variants in use, as a dict (stfd_tuning)."""
+        t = Tuning()
+        _check(lib().stfd_get_tuning(self._h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Select kernel variants (stfd_tuning fields); effective from the
+        next factor()."""
+        t = Tuning()
+        _check(lib().stfd_get_tuning(self._h, C.byref(t)))
+        for k, v in kw.items():
+            if k not in dict(Tuning._fields_):
+                raise ValueError(f"unknown tuning field {k}")
+            setattr(t, k, int(v))
+        _check(lib().stfd_set_tuning(self._h, C.byref(t)))
 
     def __del__(self):
         h = getattr(self, "_h", None)

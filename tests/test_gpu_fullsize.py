@@ -9,7 +9,7 @@ checked through properties that hold at any size:
     K_h (Kronecker identity, Sec. 3.1) and load (Sec. 2), with the GPU fed
     the oracle's time matrices and load;
   * step 3 alone (band LDL^T and both sweeps, Alg. FD step 3) on three
-    systems (smallest Re lambda, largest |lambda|, a real lambda) against the
+    systems (smallest Re lambda, largest |lambda|, the other real lambda) against the
     oracle's sparse LU solves, one by one: forward error within
     4 (b + 1) u kappa_2(S) and normwise backward error within 4 (b + 1) u
     (banded LU without pivoting, Higham Thm. 9.3, with |L||D||L^T| of the
@@ -22,8 +22,6 @@ uniform N_t = 512 and 4 right-hand sides.  The L-shape band factor holds
 6.4e9 complex entries per form, so its offsets pass 2^31.
 """
 import gc
-from concurrent.futures import ThreadPoolExecutor
-
 import numpy as np
 import pytest
 import scipy.sparse.linalg as spl
@@ -40,20 +38,19 @@ from paper_2008_01996_amd import stfd  # noqa: E402
 pytestmark = pytest.mark.gpu
 
 RTOL = 1e-10
-SOLVE_RTOL = 5e-11
+# solve tolerance, half the residual bound checked under the oracle's K_h;
+# the FP32 form's refinement stalls at 5e-11 - 6e-11 on the uniform N_t = 512
+# mesh (kappa_2(X_t) = 5.7e9), so it stops at 8e-11 there
+SOLVE_RTOL = {"fp64": 5e-11, "fp32": 8e-11}
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
-NTHREADS = 8
 
 
 def _oracle_problem(mesh, t, seeds):
+    # one load after the other: the dense products use BLAS's own threads,
+    # and BLAS is never entered from several Python threads at once
     At, Mt, Ct = tm.kernel(t)
     Mx, Ax, M10 = sm.assemble(mesh)
-
-    def one(sd):
-        return load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(sd)), Ct)
-
-    with ThreadPoolExecutor(NTHREADS) as ex:
-        Fs = list(ex.map(one, seeds))
+    Fs = [load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(sd)), Ct) for sd in seeds]
     return At, Mt, Mx, Ax, Fs
 
 
@@ -87,7 +84,7 @@ def test_full_size_residual_under_oracle_kh(name, precision):
     mesh, t, At, Mt, Mx, Ax, Fs = _case(name)
     print(f"  {name} {precision}: M_x = {Mx.shape[0]}, N_t = {At.shape[0]}, {len(Fs)} RHS", flush=True)
     sp = stfd.Space(mesh)
-    prob = stfd.Problem(sp, At, Mt, precision=precision, rtol=SOLVE_RTOL, max_refine=30)
+    prob = stfd.Problem(sp, At, Mt, precision=precision, rtol=SOLVE_RTOL[precision], max_refine=30)
     if name == "lshape128_nt1024":
         assert sp.half_band == 256 and prob.setup_report["n_sys"] == 513
     prob.factor()
@@ -99,8 +96,7 @@ def test_full_size_residual_under_oracle_kh(name, precision):
     del prob, F, U
     _free_device()
     assert rep["converged"], rep
-    with ThreadPoolExecutor(NTHREADS) as ex:
-        res = list(ex.map(lambda q: so.rel_residual(At, Mt, Mx, Ax, Fs[q], Uh[q].T), range(len(Fs))))
+    res = [so.rel_residual(At, Mt, Mx, Ax, Fs[q], Uh[q].T) for q in range(len(Fs))]
     print(f"  applications {rep['iterations']}, residual history {rep['rel_residual']}", flush=True)
     print(f"  residual under the oracle's K_h per RHS: max {max(res):.2e}, min {min(res):.2e}", flush=True)
     assert max(res) <= RTOL
@@ -136,7 +132,7 @@ def test_full_size_step3_three_systems_vs_oracle_lu(precision):
     prob.factor()
     lam = prob.system_lambdas()
     n, m, nrhs = len(lam), Mx.shape[0], 16
-    assert n == 513 and prob.setup_report["n_real"] >= 1
+    assert n == 513 and prob.setup_report["n_real"] == 2
     rng = np.random.default_rng(8500)
     G = rng.standard_normal((nrhs, 2 * n, m))
     dt = torch.float64 if precision == "fp64" else torch.float32
@@ -149,8 +145,9 @@ def test_full_size_step3_three_systems_vs_oracle_lu(precision):
     b = prob.setup_report["half_band"]
     del prob, Gd, Z
     _free_device()
-    real = [k for k in range(n) if lam[k].imag == 0.0]
-    picks = {"min Re": int(np.argmin(lam.real)), "max |lambda|": int(np.argmax(np.abs(lam))), "real": real[0]}
+    kmin = int(np.argmin(lam.real))
+    real = [k for k in range(n) if lam[k].imag == 0.0 and k != kmin]
+    picks = {"min Re": kmin, "max |lambda|": int(np.argmax(np.abs(lam))), "real": real[0]}
     u = UNIT_ROUNDOFF[precision]
     for what, k in picks.items():
         S = (Mx + lam[k] * Ax).tocsc().astype(np.complex128)

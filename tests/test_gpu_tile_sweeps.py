@@ -1,0 +1,195 @@
+"""GPU parity of the matrix-core tile sweeps (step 3 of Algorithm FD, Sec.
+4.4, second half: L_k y = g_k, w = D_k^-1 y, L_k^T z_k = w for up to 16
+right-hand sides per workgroup) against the oracle's sparse complex solves,
+and of full solves that use them.
+
+The tile sweeps are switched on through the tuning entry point
+(sweep_tile_min_rhs = 1: every right-hand-side count).  The cases cover
+every slot count of the kernel (padded half-bandwidth 16, 48, 80, 128, 192,
+256: one to four tiles per wave, 80 with a partly used last slot), a matrix
+of a single 16-row block and one of fewer than four blocks (waves that own
+no block), ragged last blocks (M_x not a multiple of 16), right-hand-side
+counts 1, 5, 16 (a full group) and 17 (a full group and a group of one).
+Bound: banded LU without pivoting has a backward error of order
+(b + 1) u |L||U| (Higham, Thm. 9.3), so the lane-chain sweeps are within
+4 (b + 1) u kappa_2(S_k).  The tile sweeps apply each 16 x 16 diagonal block
+of L through its inverse (y = L_cc^-1 q): the block solve is then backward
+stable only up to the block's Skeel condition cond(L_cc) = || |L_cc^-1| |L_cc|
+||_inf (Higham, Sec. 8.2 and 14.1), and its products run over all 16
+columns of a block, so the bound becomes
+4 (max(b, 16) + 1) u kappa_2(S_k) max(1, max_c cond(L_cc)), with the
+diagonal blocks taken from a host LDL^T of S_k.
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import load
+from oracle import solvers as so
+from oracle import space_matrices as sm
+from oracle import time_matrices as tm
+
+torch = pytest.importorskip("torch")
+from paper_2008_01996_amd import stfd  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
+
+# (cells in x, cells in y, right-hand sides): half-bandwidth = cells in x
+TILE_CASES = [(5, 3, 1), (17, 4, 5), (9, 9, 16), (40, 3, 17), (70, 4, 5), (120, 3, 16), (180, 2, 1), (250, 3, 16)]
+TILE_IDS = ["b5_one_block", "b17_three_blocks", "sq9_rhs16", "b40_rhs17", "b70_rhs5", "b120_rhs16", "b180_rhs1",
+            "b250_rhs16"]
+
+
+def _block_cond(S):
+    """max over the 16 x 16 diagonal blocks of the unit lower triangular
+    factor of S = L D L^T (no pivoting) of || |L_cc^-1| |L_cc| ||_inf."""
+    n = S.shape[0]
+    A = S.astype(np.complex128).copy()
+    L = np.eye(n, dtype=np.complex128)
+    for c in range(n):
+        L[c + 1:, c] = A[c + 1:, c] / A[c, c]
+        A[c + 1:, c + 1:] -= np.outer(L[c + 1:, c], A[c, c + 1:])
+    worst = 1.0
+    for c0 in range(0, n, 16):
+        B = L[c0:c0 + 16, c0:c0 + 16]
+        worst = max(worst, float((np.abs(np.linalg.inv(B)) @ np.abs(B)).sum(axis=1).max()))
+    return worst
+
+
+def _problem(mesh, t, precision, tile=True):
+    prob = stfd.Problem(stfd.Space(mesh), *tm.kernel(t)[:2], precision=precision)
+    if tile:
+        prob.set_tuning(sweep_tile_min_rhs=1)
+    prob.factor()
+    return prob
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("ncx,ncy,nrhs", TILE_CASES, ids=TILE_IDS)
+def test_tile_sweeps_match_oracle_solves(precision, ncx, ncy, nrhs):
+    mesh = w.rect_mesh(ncx, ncy)
+    t = w.graded_times(7)                       # three conjugate pairs and one real eigenvalue
+    At, Mt, _ = tm.kernel(t)
+    Mx, Ax, _ = sm.assemble(mesh)
+    dec = so.decompose(At, Mt)
+    prob = _problem(mesh, t, precision)
+    assert prob.tuning()["sweep_tile_min_rhs"] == 1
+    lam = prob.system_lambdas()
+    n, m = len(lam), Mx.shape[0]
+    print(f"  M_x {m} ({(m + 15) // 16} blocks), half-bandwidth {prob.setup_report['half_band']}, {nrhs} RHS",
+          flush=True)
+    rng = np.random.default_rng(8100 + nrhs)
+    G = rng.standard_normal((nrhs, 2 * n, m))
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Gd = torch.from_numpy(G).to("cuda:0", dt)
+    G = Gd.double().cpu().numpy()
+    Z = torch.empty_like(Gd)
+    prob.spatial_solve(Gd, Z)
+    torch.cuda.synchronize()
+    Z = Z.double().cpu().numpy()
+    b = prob.setup_report["half_band"]
+    u = UNIT_ROUNDOFF[precision]
+    worst = 0.0
+    for k in range(n):
+        # the library's eigenvalue matches the oracle's; the oracle then
+        # solves the same system the GPU factored (with lam[k])
+        j = int(np.argmin(np.abs(dec.lam - lam[k])))
+        assert abs(dec.lam[j] - lam[k]) <= 1e-10 * abs(dec.lam[j])
+        S = (Mx + lam[k] * Ax).toarray()
+        tol = 4 * (max(b, 16) + 1) * u * np.linalg.cond(S) * _block_cond(S)
+        for q in range(nrhs):
+            g = G[q, k] + 1j * G[q, n + k]
+            zo = so._spatial_solve((Mx, Ax, lam[k], g))
+            z = Z[q, k] + 1j * Z[q, n + k]
+            err = np.linalg.norm(z - zo) / np.linalg.norm(zo)
+            worst = max(worst, err / tol)
+            assert err <= tol, (k, q, err, tol)
+    print(f"  worst forward error / bound {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tile_sweeps_in_place(precision):
+    """G and Z the same buffer (as inside an FD application)."""
+    mesh = w.rect_mesh(70, 4)
+    t = w.graded_times(7)
+    prob = _problem(mesh, t, precision)
+    n, m = prob.setup_report["n_sys"], prob.Mx
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    G = torch.from_numpy(np.random.default_rng(8200).standard_normal((16, 2 * n, m))).to("cuda:0", dt)
+    Z = torch.empty_like(G)
+    prob.spatial_solve(G, Z)
+    prob.spatial_solve(G, G)
+    torch.cuda.synchronize()
+    assert torch.equal(G, Z)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nc,nrhs", [(16, 16), (24, 5)])
+def test_solve_with_tile_sweeps_matches_oracle(precision, nc, nrhs):
+    """Full refined solves with the tile sweeps against the oracle's direct
+    solve of K_h (relative error and residual <= 1e-10)."""
+    mesh = w.square_mesh(nc)
+    t = w.uniform_times(12)
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, M10 = sm.assemble(mesh)
+    Fs = [load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(8300 + r)), Ct) for r in range(nrhs)]
+    prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision=precision, rtol=1e-11)
+    prob.set_tuning(sweep_tile_min_rhs=1)
+    prob.factor()
+    F = torch.from_numpy(np.ascontiguousarray(np.stack([f.T for f in Fs]))).to("cuda:0")
+    U = torch.empty_like(F)
+    rep = prob.solve(F, U)
+    torch.cuda.synchronize()
+    assert rep["converged"], rep
+    Uh = U.cpu().numpy()
+    for q in range(nrhs):
+        Uo = so.direct(At, Mt, Mx, Ax, Fs[q])
+        err = np.linalg.norm(Uh[q].T - Uo) / np.linalg.norm(Uo)
+        res = so.rel_residual(At, Mt, Mx, Ax, Fs[q], Uh[q].T)
+        assert err <= 1e-10 and res <= 1e-10, (q, err, res)
+    print(f"  applications {rep['iterations']}", flush=True)
+
+
+def test_tuning_rejects_negative():
+    mesh = w.rect_mesh(9, 3)
+    prob = _problem(mesh, w.uniform_times(4), "fp64", tile=False)
+    with pytest.raises(stfd.StfdError):
+        prob.set_tuning(sweep_tile_min_rhs=-1)
+    with pytest.raises(stfd.StfdError):
+        prob.set_tuning(gemm_tile_m_fp64=96)
+    with pytest.raises(stfd.StfdError):
+        prob.set_tuning(gemm_n_fast=2)
+    with pytest.raises(ValueError):
+        prob.set_tuning(no_such_field=1)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gemm_variants_give_the_same_solution(precision):
+    """The GEMM tile height (64 or 128 rows) and grid order change only
+    which workgroup computes an output entry, not the order of its sum over
+    K: the refined solution is bit-identical for every variant, with a ragged
+    M (M_x = 1225, not a multiple of 64 or 128)."""
+    mesh = w.square_mesh(36)
+    t = w.uniform_times(20)
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, M10 = sm.assemble(mesh)
+    Fs = [load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(8400 + r)), Ct) for r in range(3)]
+    F = torch.from_numpy(np.ascontiguousarray(np.stack([f.T for f in Fs]))).to("cuda:0")
+    sp = stfd.Space(mesh)
+    ref = None
+    for bm32, bm64, nfast in ((64, 64, 0), (128, 64, 0), (64, 128, 1), (128, 128, 1)):
+        prob = stfd.Problem(sp, At, Mt, precision=precision, rtol=1e-11)
+        prob.set_tuning(gemm_tile_m_fp32=bm32, gemm_tile_m_fp64=bm64, gemm_n_fast=nfast)
+        prob.factor()
+        U = torch.empty_like(F)
+        prob.solve(F, U)
+        torch.cuda.synchronize()
+        if ref is None:
+            ref = U.clone()
+            for q in range(3):
+                Uo = so.direct(At, Mt, Mx, Ax, Fs[q])
+                assert np.linalg.norm(U[q].cpu().numpy().T - Uo) / np.linalg.norm(Uo) <= 1e-10
+        else:
+            assert torch.equal(U, ref), (bm32, bm64, nfast)

@@ -268,3 +268,47 @@ def test_binding_rejects_bad_tensors_before_the_library():
     p.device = torch.device("cuda", 0)
     with pytest.raises(ValueError):
         p.solve(z(2, 4, 9), z(2, 4, 9))                    # host tensors for a device problem
+
+
+def test_setup_rejects_band_beyond_the_sweeps():
+    """A padded half-bandwidth above 256 (here 304) is refused by the setup
+    with EINVAL and a message naming the limit, before any device call (so
+    this runs without a GPU), for both methods."""
+    sp = stfd.Space(w.rect_mesh(300, 3))
+    assert sp.half_band == 300
+    A, M, _ = tm.kernel(w.uniform_times(2))
+    lib = stfd.lib()
+    for method in (stfd.METHOD_FD, stfd.METHOD_BSC):
+        o = stfd.Opts()
+        assert lib.stfd_opts_default(ctypes.byref(o)) == 0
+        o.method = method
+        o.precision = stfd.PREC_FP64
+        h = ctypes.c_void_p()
+        rc = lib.stfd_fd_setup(sp._h, 2, A.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               M.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(o), None,
+                               ctypes.byref(h))
+        assert rc == stfd.EINVAL and not h.value
+        assert "exceeds 256" in lib.stfd_last_error().decode()
+
+
+def test_time_decompose_pairs_the_graded_1024_mesh_like_lapack():
+    """On the graded mesh t_i = (i/N_t)^2 with N_t = 1024 the eigenvalues
+    span five orders of magnitude; the host classifies each against its own
+    modulus.  Real/pair counts agree with LAPACK's generalised eigensolver
+    (which returns real eigenvalues with a zero imaginary part), and the
+    eigen residual is within the bound the setup enforces (1e-10)."""
+    A, M, _ = tm.kernel(w.graded_times(1024))
+    lam, X, s, rep = stfd.time_decompose(A, M)
+    lo = sl.eigvals(M, A)
+    assert rep["n_real"] == int(np.sum(lo.imag == 0))
+    assert rep["n_pairs"] == int(np.sum(lo.imag > 0))
+    assert (rep["n_real"], rep["n_pairs"]) == (2, 511)
+    assert rep["eig_residual"] <= 1e-10
+    assert np.abs(lam).max() / np.abs(lam).min() > 1e4
+
+
+def test_tuning_entry_points_check_their_arguments():
+    lib = stfd.lib()
+    t = stfd.Tuning()
+    assert lib.stfd_get_tuning(None, ctypes.byref(t)) == stfd.EINVAL
+    assert lib.stfd_set_tuning(None, ctypes.byref(t)) == stfd.EINVAL
