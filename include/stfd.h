@@ -37,6 +37,8 @@
 #ifndef STFD_H
 #define STFD_H
 
+#include <stddef.h>
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -359,6 +361,24 @@ int stfd_system_lambdas(const stfd_problem* p, double* lam);
  * exposed for tests (Kronecker identity of Sec. 3.1). */
 int stfd_kh_residual(stfd_problem* p, int nrhs, const double* F_dev, const double* U_dev,
                      double* R_dev, double* norms, void* hip_stream);
+
+/* stfd_kh_residual without any device allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  Same kernels and result as
+ * stfd_kh_residual: R_dev = F_dev - K_h U_dev (nrhs M_x x N_t FP64 blocks,
+ * [rhs][k][i] as everywhere, device, caller-owned).
+ * Its work memory ([M_x U | A_x U] per RHS and the per-workgroup partial
+ * sums) is a fixed array of stfd_kh_residual_noalloc_max_bytes() bytes
+ * (128 MiB) in device memory, one per GPU, held until the process ends;
+ * its device address is looked up on the first call on each device.
+ * norms_dev: NULL or 2*nrhs FP64 on the device, receiving (||R||^2, ||F||^2)
+ * per RHS; no host synchronisation.  Calls that overlap on one GPU race on
+ * the array; each call overwrites what the last one left there.
+ * Errors: STFD_EINVAL (null arguments, nrhs < 1, or more work memory than
+ * the array holds: (2 M_x N_t nrhs + 2 partials) doubles), STFD_EHIP. */
+int stfd_kh_residual_noalloc(stfd_problem* p, int nrhs, const double* F_dev, const double* U_dev,
+                             double* R_dev, double* norms_dev, void* hip_stream);
+size_t stfd_kh_residual_noalloc_max_bytes(void);
 
 /* ---------------------------------------------------------------------------
  * Per-stage device timing with HIP events recorded on the caller's stream

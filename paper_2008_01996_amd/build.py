@@ -23,7 +23,8 @@ INCLUDE = os.path.join(ROOT, "include")
 
 HOST_SOURCES = ["host_linalg.cpp", "host_time.cpp", "host_space.cpp"]
 HIP_HOST_SOURCES = ["stfd_api.cpp"]
-HIP_SOURCES = ["kernels_band.hip", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_tile.hip"]
+HIP_SOURCES = ["kernels_band.hip", "kernels_sweep.hip", "kernels_gemm.hip", "kernels_tile.hip",
+               "stfd_noalloc.hip"]
 
 ARCH = "gfx950"
 # packed FP32 instructions are switched off for all device code

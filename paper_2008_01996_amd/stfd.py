@@ -110,6 +110,9 @@ def lib():
         L.stfd_fd_setup_report.argtypes = [vp, C.POINTER(SetupReport)]
         L.stfd_fd_factor.argtypes = [vp, vp]
         L.stfd_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.stfd_kh_residual_noalloc.argtypes = [vp, C.c_int, vp, vp, vp, vp, vp]
+        L.stfd_kh_residual_noalloc_max_bytes.restype = C.c_size_t
+        L.stfd_kh_residual_noalloc_max_bytes.argtypes = []
         L.stfd_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.stfd_fd_solve.argtypes = [vp, C.c_int, vp, vp, C.POINTER(SolveReport), vp]
         L.stfd_kh_residual.argtypes = [vp, C.c_int, vp, vp, vp, dp, vp]
@@ -442,6 +445,29 @@ class Problem:
                                       C.c_void_p(R.data_ptr()), _dp(norms), C.c_void_p(_stream_ptr(stream))))
         return norms.reshape(n, 2)
 
+
+    def kh_residual_noalloc(self, F, U, R, norms=None, stream=None):
+        """R = F - K_h U on the device, with no device allocation (the work
+        memory is the library's fixed per-device array of
+        kh_residual_noalloc_max_bytes() bytes); norms: None or a float64
+        device tensor of 2 nrhs entries that receives (||R||^2, ||F||^2) per
+        RHS.  Calls that overlap on one GPU race on that array."""
+        import torch
+
+        shape = self._rhs_shape(F, "F")
+        for name, x in (("F", F), ("U", U), ("R", R)):
+            _check_tensor(name, x, torch.float64, shape, self.device)
+        if norms is not None:
+            _check_tensor("norms", norms, torch.float64, (2 * F.shape[0],), self.device)
+        _check(lib().stfd_kh_residual_noalloc(self._h, F.shape[0], C.c_void_p(F.data_ptr()),
+                                              C.c_void_p(U.data_ptr()), C.c_void_p(R.data_ptr()),
+                                              C.c_void_p(norms.data_ptr() if norms is not None else None),
+                                              C.c_void_p(_stream_ptr(stream))))
+
+
+def kh_residual_noalloc_max_bytes():
+    """Size of the fixed work array of Problem.kh_residual_noalloc."""
+    return int(lib().stfd_kh_residual_noalloc_max_bytes())
 
 class Batch:
     """Independent problems solved together (lockstep refinement, one host
