@@ -257,7 +257,9 @@ def stage_work(stage, Mx, Nt, env, nsys, nrhs, es):
     if stage in ("sweep_fwd", "sweep_bwd"):
         return "hbm", nsys * float((env + 1).sum()) * 2 * es + 2 * nsys * Mx * 2 * nrhs * es
     if stage == "fwd1":
-        return "mfma", 2.0 * Mx * (2 * Nt) * Nt * nrhs
+        # the forward transform as one product with W1 W2 (N_t x 2 n_sys),
+        # the library's form wherever its first GEMM runs in FP64
+        return "mfma", 2.0 * Mx * (2 * nsys) * Nt * nrhs
     if stage == "fwd2":
         return "mfma", 2.0 * Mx * (2 * nsys) * (2 * Nt) * nrhs
     if stage == "back":

@@ -77,7 +77,13 @@ typedef struct {
                              bit 1 = second forward GEMM (x V_t^T),
                              bit 2 = back transform (Z X^T, update of U).
                              Default 5 (first forward GEMM and back transform:
-                             their FP32 rounding is amplified by kappa_2(X_t)). */
+                             their FP32 rounding is amplified by kappa_2(X_t)).
+                             With bit 0 set (and always in the FP64 form) the
+                             two forward GEMMs are one FP64 GEMM with the
+                             product W1 W2 = A_t^-1 conj(U_t) Sigma^-1 V_t^T
+                             restricted to the systems (N_t x 2 n_sys, formed
+                             once at setup): half the flops of the first GEMM
+                             alone, and bit 1 has no effect. */
     double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
     int max_refine;       /* maximum number of refinement corrections (default 30) */
     int method;           /* STFD_METHOD_FD (default) or STFD_METHOD_BSC */

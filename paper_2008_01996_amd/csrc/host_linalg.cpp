@@ -580,4 +580,17 @@ double eig_residual(int n, const double* A, const double* M, const std::vector<c
     return res;
 }
 
+void matmul_rowmajor(int m, int k, int n, const double* A, const double* B, double* C) {
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < m; ++i) {
+        double* c = C + (size_t)i * n;
+        for (int j = 0; j < n; ++j) c[j] = 0.0;
+        for (int l = 0; l < k; ++l) {
+            const double a = A[(size_t)i * k + l];
+            const double* b = B + (size_t)l * n;
+            for (int j = 0; j < n; ++j) c[j] += a * b[j];
+        }
+    }
+}
+
 }  // namespace stfd

@@ -57,4 +57,8 @@ bool svd_jacobi(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<doubl
 bool svd_jacobi_preconditioned(int n, std::vector<cd>& a, std::vector<cd>& U, std::vector<double>& s,
                                std::vector<cd>& V, std::string* err);
 
+// C = A B for row-major real A (m x k), B (k x n), C (m x n); parallel over
+// the rows of C, each row summed over k in order.
+void matmul_rowmajor(int m, int k, int n, const double* A, const double* B, double* C);
+
 }  // namespace stfd

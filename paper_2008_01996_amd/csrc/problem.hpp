@@ -29,6 +29,8 @@ struct stfd_problem {
     void* d_W2 = nullptr;       // 2Nt x 2nsys  [[Re, Im], [-Im, Re]] of V_t^T[:, sys], working precision
     void* d_Xb = nullptr;       // 2nsys x Nt   [Re; -Im] of c_k x_k^T, working precision
     double* d_W2d = nullptr;    // FP64 copies for FP64 transforms in the FP32 form
+    double* d_Wfwd = nullptr;   // Nt x 2nsys FP64: W1 W2, the forward transform as one product
+    bool fwd_merged = false;    // forward transform: one FP64 GEMM with d_Wfwd (else W1, then W2)
     double* d_Xbd = nullptr;
     double* d_Bres = nullptr;   // 2Nt x Nt     [A_t^T; M_t^T]
     double* d_S = nullptr;      // Alg. BSc: Nt x Nt upper-triangular Schur factor, complex interleaved

@@ -246,7 +246,7 @@ int ensure_work(stfd_problem* p, int nrhs) {
     const size_t es = is_fp32(p) ? 4 : 8;
     const size_t parts = std::max(stfd::gemm_resid_partials(p->Mx, p->Nt, nrhs), (size_t)1);
     struct { void** ptr; size_t bytes; } req[] = {
-        {&p->d_T1, Mx * 2 * Nt * es * nrhs},
+        {&p->d_T1, p->fwd_merged ? 0 : Mx * 2 * Nt * es * nrhs},
         {&p->d_G, Mx * 2 * ns * es * nrhs},
         {&p->d_Gs, p->opts.inner_refine > 0 ? Mx * 2 * ns * es * nrhs : 0},
         {reinterpret_cast<void**>(&p->d_P), Mx * 2 * Nt * 8 * nrhs},
@@ -631,6 +631,16 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
             Bres[(size_t)(n + j) * n + k] = Mt[(size_t)k * n + j];
         }
     std::vector<float> W2f(W2h.begin(), W2h.end()), Xbf(Xbh.begin(), Xbh.end());
+    // the forward transform X^-T restricted to the systems as one FP64
+    // product W1 W2 (Nt x 2nsys): one GEMM of 2 M_x N_t 2 n_sys flops per
+    // RHS in place of two of 2 M_x N_t 2 N_t each, wherever the first of
+    // them would run in FP64 (the FP64 form, and the FP32 form's default)
+    p->fwd_merged = !f32 || (o.fp64_transforms & 1);
+    std::vector<double> Wfwd;
+    if (p->fwd_merged) {
+        Wfwd.resize((size_t)n * 2 * ns);
+        stfd::matmul_rowmajor(n, 2 * n, 2 * ns, W1h.data(), W2h.data(), Wfwd.data());
+    }
 
     const stfd_space* s = space;
     int e = 0;
@@ -645,18 +655,21 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
         stfd_problem_free(p);
         return e;
     }
+    if (p->fwd_merged && (e = upload(&p->d_Wfwd, Wfwd.data(), Wfwd.size() * sizeof(double), st))) {
+        stfd_problem_free(p);
+        return e;
+    }
     if (f32) {
-        if ((e = upload(&p->d_W1f, W1f.data(), W1f.size() * sizeof(float), st)) ||
-            (e = upload(&p->d_W2, W2f.data(), W2f.size() * sizeof(float), st)) ||
+        if ((!p->fwd_merged && ((e = upload(&p->d_W1f, W1f.data(), W1f.size() * sizeof(float), st)) ||
+                                (e = upload(&p->d_W2, W2f.data(), W2f.size() * sizeof(float), st)) ||
+                                (e = upload(&p->d_W2d, W2h.data(), W2h.size() * sizeof(double), st)))) ||
             (e = upload(&p->d_Xb, Xbf.data(), Xbf.size() * sizeof(float), st)) ||
-            (e = upload(&p->d_W2d, W2h.data(), W2h.size() * sizeof(double), st)) ||
             (e = upload(&p->d_Xbd, Xbh.data(), Xbh.size() * sizeof(double), st))) {
             stfd_problem_free(p);
             return e;
         }
     } else {
-        if ((e = upload(&p->d_W2, W2h.data(), W2h.size() * sizeof(double), st)) ||
-            (e = upload(&p->d_Xb, Xbh.data(), Xbh.size() * sizeof(double), st))) {
+        if ((e = upload(&p->d_Xb, Xbh.data(), Xbh.size() * sizeof(double), st))) {
             stfd_problem_free(p);
             return e;
         }
@@ -815,14 +828,30 @@ hipError_t launch_gemm_tuned(const stfd_problem* p, stfd::GemmKind kind, const s
     return stfd::launch_gemm(kind, g, st);
 }
 
+int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st);
+
 // one FD application: X (FP64 residual or load, Mx x Nt per RHS) -> U += alpha FD(X)
 int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t st) {
     const bool f32 = is_fp32(p);
     const int Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
+    const bool inner = p->opts.inner_refine > 0;
+    const int mask = f32 ? p->opts.fp64_transforms : 7;
     stfd::GemmArgs g{};
+    if (p->fwd_merged) {
+        // step 2: G = X (W1 W2)   (Mx x 2nsys), FP64 products, G stored in
+        // the working precision
+        g.A = X; g.B = p->d_Wfwd; g.C = inner ? p->d_Gs : p->d_G;
+        g.M = Mx; g.N = 2 * ns; g.K = Nt;
+        g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
+        g.strideA = (long long)Mx * Nt; g.strideC = (long long)Mx * 2 * ns;
+        g.batch = nrhs;
+        StageTimer tm(p, STFD_ST_FWD1, st);
+        HIPCHK(launch_gemm_tuned(p, f32 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
+               "forward transform");
+        return fd_apply_rest(p, nrhs, U, st);
+    }
     // step 2a: T1 = X W1   (Mx x 2Nt)
     g.A = X;
-    const int mask = f32 ? p->opts.fp64_transforms : 7;
     g.B = (f32 && !(mask & 1)) ? static_cast<const void*>(p->d_W1f) : static_cast<const void*>(p->d_W1);
     g.C = p->d_T1;
     g.M = Mx; g.N = 2 * Nt; g.K = Nt;
@@ -836,7 +865,6 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     }
     // step 2b: G = T1 W2   (Mx x 2nsys)
     g = stfd::GemmArgs{};
-    const bool inner = p->opts.inner_refine > 0;
     g.A = p->d_T1; g.B = (f32 && (mask & 2)) ? static_cast<const void*>(p->d_W2d) : p->d_W2;
     g.C = inner ? p->d_Gs : p->d_G;
     g.M = Mx; g.N = 2 * ns; g.K = 2 * Nt;
@@ -850,6 +878,17 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
                                  g, st),
                "forward transform 2");
     }
+    return fd_apply_rest(p, nrhs, U, st);
+}
+
+// steps 3 and 4 of an FD application, from G (or Gs with the inner
+// refinement) to U += Re(Z Xb)
+int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
+    const bool f32 = is_fp32(p);
+    const int Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
+    const bool inner = p->opts.inner_refine > 0;
+    const int mask = f32 ? p->opts.fp64_transforms : 7;
+    stfd::GemmArgs g{};
     // step 3: spatial solves, in place in G (with the inner refinement: G
     // kept in Gs, Z into G; then Gs -= S_k Z in FP64, solved in place, and
     // the correction added to Z)
@@ -1497,6 +1536,7 @@ extern "C" void stfd_problem_free(stfd_problem* p) {
     (void)hipFree(p->d_W2);
     (void)hipFree(p->d_Xb);
     (void)hipFree(p->d_W2d);
+    (void)hipFree(p->d_Wfwd);
     (void)hipFree(p->d_Xbd);
     (void)hipFree(p->d_Bres);
     (void)hipFree(p->d_S);

@@ -359,9 +359,11 @@ def test_fp32_forward_variant_still_converges():
     _check(At, Mt, Mx, Ax, Fs, Us, rep)
 
 
-@pytest.mark.parametrize("mask", [1, 3, 7])
+@pytest.mark.parametrize("mask", [1, 2, 3, 6, 7])
 def test_fp64_transform_variants(mask):
-    """The FP32 form with other transform GEMMs on FP64 matrix cores."""
+    """The FP32 form with other transform GEMMs on FP64 matrix cores: with
+    bit 0 the forward transform is one FP64 GEMM with W1 W2, without it the
+    two GEMMs (the first in FP32)."""
     mesh = w.square_mesh(12)
     t = w.graded_times(24)
     At, Mt, Mx, Ax, Fs = _oracle_case(mesh, t, "random", seeds=[11, 12])
