@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restri
         const int r = e >> 4, c = e & 15, d = r - c;
         const bool ok = c < Mx && d >= 0 && d <= bp;
         const cplx<T>* x = base + (ok ? (size_t)c * bp1 + d : 0);
-        PB[0][r * RPS + c] = ok ? cplx<T>{x->re, x->im} : zero;
+        PB[0][r * RPS + c] = cplx<T>{ok ? x->re : T(0), ok ? x->im : T(0)};
     }
 
     if (wave >= 4) {
@@ -542,7 +542,7 @@ __global__ void __launch_bounds__(512) band_ldl_reg_kernel(cplx<float>* __restri
                         }
                     }
                 }
-                P[r8r * RPS + r8c] = row8_ok(q) ? r8 : zero;
+                P[r8r * RPS + r8c] = cplx<T>{row8_ok(q) ? r8.re : T(0), row8_ok(q) ? r8.im : T(0)};
                 prefetch(q + 9);                          // for the next hand-over
                 r8 = row8_load(q + 1);
             }
@@ -683,6 +683,13 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
     cplx<T>* PL = reinterpret_cast<cplx<T>*>(smem_raw);   // L of the rows below the diagonal block
     cplx<T>* NX = PL + 256 * PS;                          // hand-over: the next panel's updated rows
     cplx<T>* PD = NX + 256 * PS;                          // D of the panel
+    // (complex values as 2-vectors: builtin assignment through the typed
+    // pointers)
+    using V2 = T __attribute__((ext_vector_type(2)));
+    using LdsV2 = __attribute__((address_space(3))) V2;
+    using GlbV2 = __attribute__((address_space(1))) V2;
+    LdsV2* NXs = (LdsV2*)NX;
+    GlbV2* gbase = (GlbV2*)base;
     const int bp1 = bp + 1;
     const int NB = bp / 16;
     const int tid = threadIdx.x;
@@ -699,21 +706,24 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
         const int d = rrel - c;
         return own && rrel < nrow && d >= 0 && d <= bp && p0 + rrel < Mx && p0 + c < Mx;
     };
-    auto ent_addr = [&](int p0, int c, int nrow) -> size_t {
-        return ent_on(p0, c, nrow) ? (size_t)(p0 + c) * bp1 + (rrel - c) : 0;
+    // (offsets within one system fit in 32 bits: M_x (bp + 1) < 2^31, checked
+    // by the launcher; 32-bit selects keep the address arithmetic branch-free)
+    auto ent_off = [&](int p0, int c, int nrow, int lo) -> int {
+        return ent_on(p0, c, nrow) && rrel >= lo ? (p0 + c) * bp1 + (rrel - c) : 0;
     };
-    // raw loads of this lane's row of panel starting at p0 (rows < nrow)
+    // raw loads of this lane's row of panel starting at p0 (rows lo .. nrow - 1;
+    // every lane loads, the others from offset 0)
     cplx<T> pf[16];
-    auto prefetch = [&](int p0, int nrow) {
+    auto prefetch = [&](int p0, int nrow, int lo) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-            const cplx<T>* e = base + ent_addr(p0, c, nrow);
+            const cplx<T>* e = base + ent_off(p0, c, nrow, lo);
             pf[c].re = e->re;
             pf[c].im = e->im;
         }
     };
     int nr_prev = 0;                                      // row blocks the previous panel updated
-    prefetch(0, nblk > 0 ? 16 + 16 * min(NB, reach[0]) : 0);
+    prefetch(0, nblk > 0 ? 16 + 16 * min(NB, reach[0]) : 0, 0);
 
     for (int q = 0; q < nblk; ++q) {
         const int p0 = 16 * q;
@@ -736,7 +746,7 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
             const int nrow1 = 16 + 16 * min(NB, reach[q + 1]);
             // rows of panel q + 1 at or beyond 16 nr (relative to its start)
             // are untouched by any earlier panel
-            if (rrel >= 16 * nr) prefetch(p0 + 16, nrow1);
+            prefetch(p0 + 16, nrow1, 16 * nr);
         }
         // ---- 2. factor the panel in registers
         int bad = 0;
@@ -771,12 +781,27 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
         const bool writer = own && (lane >= 16 || wave == 0);
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-            if (writer && c < nb && ent_on(p0, c, nrow)) base[(size_t)(p0 + c) * bp1 + (rrel - c)] = a[c];
+            if (writer && c < nb && ent_on(p0, c, nrow)) base[(p0 + c) * bp1 + (rrel - c)] = a[c];
         if (own && lane >= 16) {
 #pragma unroll
-            for (int c = 0; c < 16; ++c) PL[(rrel - 16) * PS + c] = rrel < nrow ? a[c] : zero;
+            for (int c = 0; c < 16; ++c) {
+                // component-wise selects (a select of whole structs becomes a
+                // load through a selected address, with a[] in scratch memory)
+                const bool in = rrel < nrow;
+                PL[(rrel - 16) * PS + c] = cplx<T>{in ? a[c].re : T(0), in ? a[c].im : T(0)};
+            }
         }
-        if (wave == 0 && lane < 16) PD[lane] = a[lane];
+        {
+            // the diagonal entry a[lane] of this lane's row, by selects (an
+            // index by lane would put a[] in scratch memory)
+            cplx<T> dg = a[0];
+#pragma unroll
+            for (int c = 1; c < 16; ++c) {
+                dg.re = lane == c ? a[c].re : dg.re;
+                dg.im = lane == c ? a[c].im : dg.im;
+            }
+            if (wave == 0 && lane < 16) PD[lane] = dg;
+        }
         __syncthreads();
         // ---- 4. trailing tiles, wave w takes tiles w, w + 8, ...
         const int ntile = nr * (nr + 1) / 2;
@@ -792,13 +817,17 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
             const int d = r - cc;
             return d >= 0 && d <= bp && r < Mx && cc < Mx;
         };
+        // raw loads of tile t (t >= ntile: of the last tile, the values
+        // unused; one address pattern for every call keeps the loads in
+        // flight without waits)
         auto c_load = [&](int t, cplx<T> (&cv)[4]) {
             int ti, tj;
-            tile_ij(t < ntile ? t : 0, ti, tj);
+            tile_ij(min(t, ntile - 1), ti, tj);
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int r = p0 + 16 + 16 * ti + li, cc = p0 + 16 + 16 * tj + mfma_row<T>(lk, j);
-                const cplx<T>* e = base + (t < ntile && c_on(ti, tj, j) ? (size_t)cc * bp1 + (r - cc) : 0);
+                const int off = c_on(ti, tj, j) ? cc * bp1 + (r - cc) : 0;
+                const cplx<T>* e = base + off;
                 cv[j].re = e->re;
                 cv[j].im = e->im;
             }
@@ -824,32 +853,40 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
                     ui = mfma16x16x4<T>(x.im, y.re, ui);
                 }
             }
+            // the LDS and HBM stores through pointers of their own address
+            // spaces: one store through a generic pointer for both (which
+            // the compiler would otherwise make of the two branches) waits
+            // on every load in flight
+            if (tj == 0) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (!c_on(ti, tj, j)) continue;
-                const cplx<T> v = {cv[j].re - ur[j], cv[j].im - ui[j]};
-                if (tj == 0) {
-                    NX[(16 * ti + li) * PS + mfma_row<T>(lk, j)] = v;           // the next panel
-                } else {
+                for (int j = 0; j < 4; ++j)
+                    if (c_on(ti, tj, j))
+                        NXs[(16 * ti + li) * PS + mfma_row<T>(lk, j)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
                     const int r = p0 + 16 + 16 * ti + li, cc = p0 + 16 + 16 * tj + mfma_row<T>(lk, j);
-                    base[(size_t)cc * bp1 + (r - cc)] = v;
+                    if (c_on(ti, tj, j)) gbase[cc * bp1 + (r - cc)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
                 }
             }
         };
         {
-            cplx<T> c0[4], c1[4];
+            // NB tile buffers in straight-line code (each a fixed set of
+            // registers): the loads of the wave's next NB - 1 tiles are in
+            // flight while a tile is updated (FP32 3, FP64 2); the loads are
+            // unconditional, only the update is skipped past the last tile
+            constexpr int NB = sizeof(T) == 4 ? 4 : 3;
+            cplx<T> cb[NB][4];
             int t = wave;
-            c_load(t, c0);
-            // two tiles per round in straight-line code (each buffer a fixed
-            // set of registers), the next tile's loads in flight
+#pragma unroll
+            for (int i = 0; i + 1 < NB; ++i) c_load(t + 8 * i, cb[i]);
             while (t < ntile) {
-                c_load(t + 8, c1);
-                c_update(t, c0);
-                t += 8;
-                if (t >= ntile) break;
-                c_load(t + 8, c0);
-                c_update(t, c1);
-                t += 8;
+#pragma unroll
+                for (int i = 0; i < NB; ++i) {
+                    c_load(t + 8 * (NB - 1), cb[(i + NB - 1) % NB]);
+                    if (t < ntile) c_update(t, cb[i]);
+                    t += 8;
+                }
             }
         }
         nr_prev = nr;
@@ -914,7 +951,7 @@ hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int nreal, const 
     const int ncplx = nsys - nreal;
     const int nwg = ncplx + (nreal + 1) / 2;
     if (kernel == FACTOR_PANEL || (kernel == FACTOR_AUTO && !use_window<T>(bp) && !(sizeof(T) == 4 && bp == 128))) {
-        if (bp > 256 || bp % 16 != 0) return hipErrorInvalidValue;
+        if (bp > 256 || bp % 16 != 0 || (size_t)Mx * (bp + 1) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
         const size_t smem = panel_smem<T>();
         hipError_t e = hipFuncSetAttribute((const void*)band_ldl_panel_kernel<T>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
