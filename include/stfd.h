@@ -280,7 +280,10 @@ int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* rep);
  *                       lane-chain sweeps, one system at a time).
  *   gemm_tile_m_fp32    rows of the workgroup tile of the transform GEMMs
  *   gemm_tile_m_fp64    (Alg. FD steps 2 and 4) on FP32 and on FP64 matrix
- *                       cores: 64 or 128 (the residual GEMM keeps 64).
+ *                       cores: 64 or 128.
+ *   gemm_tile_n_fp64    its columns on FP64 matrix cores: 64, or 128 with
+ *                       128 rows (default 128 x 128; the residual GEMM
+ *                       always takes the 128 x 128 tile).
  *   gemm_n_fast         1: consecutive workgroups of a GEMM walk along its
  *                       columns (those sharing a panel of the space-time
  *                       block run side by side); 0: along its rows.
@@ -309,6 +312,7 @@ typedef struct {
     int gemm_n_fast;
     int factor_kernel;
     int factor_pack_real;
+    int gemm_tile_n_fp64;
 } stfd_tuning;
 
 int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t);

@@ -9,8 +9,8 @@ For a problem shape it times the variants on the GPU and keeps the fastest:
   * the band factor (step 3, first half): the panel kernel against the
     streaming one, where no on-chip window kernel applies;
   * the transform GEMMs (steps 2 and 4): workgroup tile height 64 or 128 on
-    FP32 and on FP64 matrix cores, and the grid order, timed as the full
-    application of the problem's transforms.
+    FP32 matrix cores, 64 x 64, 128 x 64 or 128 x 128 on FP64 ones, and the
+    grid order, timed as the full application of the problem's transforms.
 
 Results go to a JSON cache keyed by the shape bucket (precision, padded
 half-bandwidth, M_x and N_t rounded to powers of two).  The binding applies
@@ -35,7 +35,10 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(HERE, "tune_cache.json")
 CACHE_ENV = "STFD_TUNE_CACHE"
-FIELDS = ("sweep_tile_min_rhs", "gemm_tile_m_fp32", "gemm_tile_m_fp64", "gemm_n_fast", "factor_kernel")
+FIELDS = ("sweep_tile_min_rhs", "gemm_tile_m_fp32", "gemm_tile_m_fp64", "gemm_tile_n_fp64", "gemm_n_fast",
+          "factor_kernel")
+# FP64 GEMM workgroup tiles (rows, columns) the tuner tries
+FP64_TILES = ((64, 64), (128, 64), (128, 128))
 RHS_COUNTS = (1, 2, 4, 8, 16)
 
 
@@ -94,7 +97,9 @@ def apply(problem, entries: dict | None = None) -> dict | None:
     rep = problem.setup_report
     t = lookup(entries, problem.precision, problem.Mx, rep["half_band"], problem.Nt)
     if t:
-        problem.set_tuning(**{k: v for k, v in t.items() if k in FIELDS})
+        t = {k: v for k, v in t.items() if k in FIELDS}
+        t.setdefault("gemm_tile_n_fp64", 64)      # entries from before the 128 x 128 tile
+        problem.set_tuning(**t)
     return t
 
 
@@ -163,15 +168,15 @@ def tune_problem(prob, F, reps: int = 3, rhs_counts=RHS_COUNTS, log=print) -> di
     U = torch.empty_like(F)
     best, best_ms = None, None
     for bm32 in (64, 128):
-        for bm64 in (64, 128):
+        for bm64, bn64 in FP64_TILES:
             for nfast in (0, 1):
                 t = {"sweep_tile_min_rhs": tile_min, "gemm_tile_m_fp32": bm32, "gemm_tile_m_fp64": bm64,
-                     "gemm_n_fast": nfast, "factor_kernel": factor_kernel}
+                     "gemm_tile_n_fp64": bn64, "gemm_n_fast": nfast, "factor_kernel": factor_kernel}
                 prob.set_tuning(**t)
                 prob.factor()
                 ms = _time(lambda: prob.apply(X, U), reps)
-                measured["apply_ms"][f"bm32={bm32},bm64={bm64},nfast={nfast}"] = ms
-                log(f"  application ({nr} RHS), GEMM tiles {bm32}/{bm64}, n-fast {nfast}: {ms:.2f} ms")
+                measured["apply_ms"][f"bm32={bm32},fp64 tile={bm64}x{bn64},nfast={nfast}"] = ms
+                log(f"  application ({nr} RHS), GEMM tiles {bm32} / {bm64}x{bn64}, n-fast {nfast}: {ms:.2f} ms")
                 if best_ms is None or ms < best_ms:
                     best, best_ms = t, ms
     prob.set_tuning(**best)

@@ -26,7 +26,8 @@ struct GemmArgs {
     int batch;
     double alpha;
     const int* gate;    // launch_gate() at launch: the kernel returns at once while *gate != 0
-    int bm;             // workgroup tile height: 64 (default) or 128 (not for EPI_RESID)
+    int bm;             // workgroup tile: 64 x 64, 128 x 64, or 0: 128 x 128 (FP64 matrix cores only;
+                        // the residual always takes the 128 x 128 tile)
     int nfast;          // 1: consecutive workgroups run along N (share an A panel)
 };
 

@@ -134,6 +134,162 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP64-accumulating GEMMs with a 128 x 128 workgroup tile: 4 waves of 64 x 64
+// (4 x 4 FP64 16x16x4 MFMA tiles each, 128 accumulator registers), K in
+// steps of 16 through a double-buffered LDS (one barrier per step), the next
+// step's tiles loaded into registers while the current one is on the matrix
+// cores.  Against the 64 x 64 tile it halves the bytes per flop that every
+// workgroup pulls through L2 (the small time-side factor B, re-read for
+// every row panel, is the larger share).
+//
+// Tile order: workgroup i runs on XCD i mod 8; each XCD gets a contiguous
+// range of the logical tiles.  Within a right-hand side the logical tiles
+// run through groups of GM row panels: down the GM panels of one N tile,
+// then the next N tile.  The 64 workgroups an XCD holds at once (32 CUs, two
+// each) so cover about 8 row panels x 8 N tiles and share their A panels and
+// B slabs in that XCD's L2: A and B each come from HBM about once per group
+// instead of once per tile (rocprofv3 FETCH_SIZE of the 64 x 64 kernel,
+// whose neighbouring tiles sit on different XCDs: 6.9x the algorithmic
+// bytes for the residual GEMM, 20x for the forward transform).
+// ---------------------------------------------------------------------------
+constexpr int WBM = 128, WBN = 128, WPAD = 2, NXCD = 8, WGM = 8;
+
+__host__ __device__ inline unsigned wide_tiles(int M, int N) {
+    return (unsigned)((M + WBM - 1) / WBM) * (unsigned)((N + WBN - 1) / WBN);
+}
+
+template <typename TA, int EPI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) gemm_wide_kernel(GemmArgs g) {
+    if (g.gate && *g.gate) return;
+    __shared__ double As[2][BK][WBM + WPAD];
+    __shared__ double Bs[2][BK][WBN + WPAD];
+    __shared__ double red[8];
+    const unsigned per = wide_tiles(g.M, g.N);
+    const unsigned total = per * (unsigned)g.batch;
+    const unsigned per_xcd = (total + NXCD - 1) / NXCD;
+    const unsigned logical = (blockIdx.x % NXCD) * per_xcd + blockIdx.x / NXCD;
+    if (logical >= total) return;
+    const int batch = (int)(logical / per);
+    const unsigned tile = logical % per;
+    const int nt = (g.N + WBN - 1) / WBN, mt = (g.M + WBM - 1) / WBM;
+    const int group = (int)(tile / (WGM * nt)), first_m = group * WGM;
+    const int gsz = min(mt - first_m, WGM);
+    const int in_group = (int)(tile % (WGM * nt));
+    const int m0 = (first_m + in_group % gsz) * WBM, n0 = (in_group / gsz) * WBN;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const TA* A = static_cast<const TA*>(g.A) + (size_t)batch * g.strideA;
+    const double* B = static_cast<const double*>(g.B);
+
+    typename vec4<double>::type acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = zero4<double>();
+
+    // global -> registers: thread t loads rows / columns (t & 127) of k rows
+    // (t >> 7) + 2 i; addresses clamped into the matrices, the values past
+    // their edges replaced by zeros when they go to LDS
+    const int lr = tid & 127, lh = tid >> 7;
+    const int gm = min(m0 + lr, g.M - 1), gn = min(n0 + lr, g.N - 1);
+    const bool m_in = m0 + lr < g.M, n_in = n0 + lr < g.N;
+    TA ra[8];
+    double rb[8];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int gk = min(k0 + lh + 2 * i, g.K - 1);
+            ra[i] = A[(size_t)gm + (size_t)gk * g.lda];
+            rb[i] = B[(size_t)gk * g.ldb + gn];
+        }
+    };
+    auto stash = [&](int buf, int k0) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int k = lh + 2 * i;
+            const bool k_in = k0 + k < g.K;
+            As[buf][k][lr] = m_in && k_in ? static_cast<double>(ra[i]) : 0.0;
+            Bs[buf][k][lr] = n_in && k_in ? rb[i] : 0.0;
+        }
+    };
+    load(0);
+    stash(0, 0);
+    __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < g.K; k0 += BK) {
+        const bool more = k0 + BK < g.K;
+        if (more) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const int k = 4 * kk + lk;
+            double bf[4], af[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                bf[t] = Bs[buf][k][wn + 16 * t + li];
+                af[t] = As[buf][k][wm + 16 * t + li];
+            }
+#pragma unroll
+            for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+                for (int tm = 0; tm < 4; ++tm) acc[tn][tm] = mfma16x16x4<double>(bf[tn], af[tm], acc[tn][tm]);
+        }
+        if (more) stash(buf ^ 1, k0 + BK);
+        __syncthreads();
+        buf ^= 1;
+    }
+
+    // epilogue: acc[tn][tm][j] = C[m = m0 + wm + 16 tm + li][n = n0 + wn + 16 tn + mfma_row(lk, j)]
+    double s_r = 0.0, s_f = 0.0;
+#pragma unroll
+    for (int tn = 0; tn < 4; ++tn)
+#pragma unroll
+        for (int tm = 0; tm < 4; ++tm)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = m0 + wm + 16 * tm + li;
+                const int n = n0 + wn + 16 * tn + mfma_row<double>(lk, j);
+                if (m >= g.M || n >= g.N) continue;
+                const size_t off = (size_t)batch * g.strideC + (size_t)m + (size_t)n * g.ldc;
+                const double v = acc[tn][tm][j];
+                if (EPI == EPI_STORE_F32) {
+                    static_cast<float*>(g.C)[off] = static_cast<float>(v);
+                } else if (EPI == EPI_STORE_F64) {
+                    static_cast<double*>(g.C)[off] = v;
+                } else if (EPI == EPI_ADD_F64) {
+                    static_cast<double*>(g.C)[off] += g.alpha * v;
+                } else {   // EPI_RESID: C = F - A B, sums of squares of C and F
+                    const size_t foff = (size_t)batch * g.strideF + (size_t)m + (size_t)n * g.ldc;
+                    const double f = static_cast<const double*>(g.F)[foff];
+                    const double r = f - v;
+                    static_cast<double*>(g.C)[off] = r;
+                    s_r += r * r;
+                    s_f += f * f;
+                }
+            }
+    if (EPI == EPI_RESID) {
+        const double tr = block_sum(s_r, red);
+        const double tf = block_sum(s_f, red);
+        if (tid == 0) {
+            // (the partials of a RHS are summed in full, in any block order)
+            const size_t idx = (size_t)batch * per + tile;
+            g.partial[2 * idx] = tr;
+            g.partial[2 * idx + 1] = tf;
+        }
+    }
+}
+
+template <typename TA, int EPI>
+static hipError_t launch_gemm_wide(const GemmArgs& g, hipStream_t st) {
+    const unsigned total = wide_tiles(g.M, g.N) * (unsigned)g.batch;
+    const unsigned grid = NXCD * ((total + NXCD - 1) / NXCD);
+    hipLaunchKernelGGL((gemm_wide_kernel<TA, EPI>), dim3(grid), dim3(256), 0, st, g);
+    return hipGetLastError();
+}
+
 template <typename TA, typename TC, int EPI, int TM, bool NFAST>
 static hipError_t launch_gemm_v(const GemmArgs& g, hipStream_t st) {
     const unsigned mt = (g.M + 32 * TM - 1) / (32 * TM), nt = (g.N + BN - 1) / BN;
@@ -147,7 +303,12 @@ template <typename TA, typename TC, int EPI>
 static hipError_t launch_gemm_t(const GemmArgs& g0, hipStream_t st) {
     GemmArgs g = g0;
     g.gate = launch_gate();
-    if (EPI == EPI_RESID && g.bm == 128) g.bm = 64;   // its partials are counted for the 64-row tile
+    if constexpr (sizeof(TC) == 8) {
+        // the residual always takes the 128 x 128 tile (its partials are
+        // counted for it); the others where chosen (bm = 0)
+        if (EPI == EPI_RESID || g.bm == 0) return launch_gemm_wide<TA, EPI>(g, st);
+    }
+    if (g.bm == 0) g.bm = 64;
     if (g.bm == 128)
         return g.nfast ? launch_gemm_v<TA, TC, EPI, 4, true>(g, st) : launch_gemm_v<TA, TC, EPI, 4, false>(g, st);
     return g.nfast ? launch_gemm_v<TA, TC, EPI, 2, true>(g, st) : launch_gemm_v<TA, TC, EPI, 2, false>(g, st);
@@ -169,7 +330,7 @@ hipError_t launch_gemm(GemmKind kind, const GemmArgs& g, hipStream_t st) {
 }
 
 size_t gemm_resid_partials(int M, int N, int batch) {
-    return (size_t)((M + 63) / 64) * ((N + BN - 1) / BN) * batch;
+    return (size_t)wide_tiles(M, N) * batch;
 }
 
 // ---------------------------------------------------------------------------

@@ -37,7 +37,8 @@ struct stfd_problem {
     void* d_LB = nullptr;       // band factors
     void* d_LI = nullptr;       // inverses of their 16 x 16 diagonal blocks (tile sweeps)
     int tile_min_rhs = 0;       // tile sweeps from this many right-hand sides on (0: never)
-    int gemm_bm[2] = {64, 64};  // GEMM tile rows on FP32 / FP64 matrix cores
+    int gemm_bm[2] = {64, 128}; // GEMM tile rows on FP32 / FP64 matrix cores
+    int gemm_bn64 = 128;        // GEMM tile columns on FP64 matrix cores (128: the 128 x 128 tile)
     int gemm_nfast = 0;         // GEMM grid order
     int factor_kernel = 0;      // band factor kernel (stfd_tuning.factor_kernel)
     int factor_pack_real = 1;   // real systems two to a workgroup (stfd_tuning.factor_pack_real)

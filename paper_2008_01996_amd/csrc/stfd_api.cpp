@@ -714,6 +714,7 @@ extern "C" int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t) {
     t->sweep_tile_min_rhs = p->tile_min_rhs;
     t->gemm_tile_m_fp32 = p->gemm_bm[0];
     t->gemm_tile_m_fp64 = p->gemm_bm[1];
+    t->gemm_tile_n_fp64 = p->gemm_bn64;
     t->gemm_n_fast = p->gemm_nfast;
     t->factor_kernel = p->factor_kernel;
     t->factor_pack_real = p->factor_pack_real;
@@ -724,11 +725,13 @@ extern "C" int stfd_set_tuning(stfd_problem* p, const stfd_tuning* t) {
     auto tile_ok = [](int m) { return m == 64 || m == 128; };
     if (!p || !t || t->sweep_tile_min_rhs < 0 || !tile_ok(t->gemm_tile_m_fp32) || !tile_ok(t->gemm_tile_m_fp64) ||
         (t->gemm_n_fast != 0 && t->gemm_n_fast != 1) || t->factor_kernel < 0 || t->factor_kernel > 2 ||
-        (t->factor_pack_real != 0 && t->factor_pack_real != 1))
+        (t->factor_pack_real != 0 && t->factor_pack_real != 1) ||
+        (t->gemm_tile_n_fp64 != 64 && !(t->gemm_tile_n_fp64 == 128 && t->gemm_tile_m_fp64 == 128)))
         return fail(STFD_EINVAL, "set_tuning: bad arguments");
     drop_graphs(p);                     // captured rounds hold the old kernel choice
     p->gemm_bm[0] = t->gemm_tile_m_fp32;
     p->gemm_bm[1] = t->gemm_tile_m_fp64;
+    p->gemm_bn64 = t->gemm_tile_n_fp64;
     p->gemm_nfast = t->gemm_n_fast;
     p->factor_kernel = t->factor_kernel;
     p->factor_pack_real = t->factor_pack_real;
@@ -824,6 +827,7 @@ hipError_t launch_gemm_tuned(const stfd_problem* p, stfd::GemmKind kind, const s
     stfd::GemmArgs g = g0;
     const bool mfma32 = kind == stfd::GEMM_D_F_STORE_F || kind == stfd::GEMM_F_F_STORE_F || kind == stfd::GEMM_F_F_ADD_D;
     g.bm = p->gemm_bm[mfma32 ? 0 : 1];
+    if (!mfma32 && g.bm == 128 && p->gemm_bn64 == 128) g.bm = 0;   // the 128 x 128 tile
     g.nfast = p->gemm_nfast;
     return stfd::launch_gemm(kind, g, st);
 }
@@ -845,9 +849,11 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
         g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
         g.strideA = (long long)Mx * Nt; g.strideC = (long long)Mx * 2 * ns;
         g.batch = nrhs;
-        StageTimer tm(p, STFD_ST_FWD1, st);
-        HIPCHK(launch_gemm_tuned(p, f32 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
-               "forward transform");
+        {
+            StageTimer tm(p, STFD_ST_FWD1, st);
+            HIPCHK(launch_gemm_tuned(p, f32 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
+                   "forward transform");
+        }
         return fd_apply_rest(p, nrhs, U, st);
     }
     // step 2a: T1 = X W1   (Mx x 2Nt)

@@ -40,7 +40,9 @@ def test_entry_selects_its_variant(tmp_path, monkeypatch):
     monkeypatch.setenv(autotune.CACHE_ENV, str(path))
     p = _Stub("fp32", 48641, 256, 1024)
     got = autotune.apply(p)
-    assert p.applied == ENTRIES["fp32/bp256/mx65536/nt1024"]["tuning"] == got
+    # an entry without the FP64 tile width keeps the 64-column tile it was tuned with
+    want = dict(ENTRIES["fp32/bp256/mx65536/nt1024"]["tuning"], gemm_tile_n_fp64=64)
+    assert p.applied == want == got
 
 
 def test_nearest_bucket_and_no_match():
@@ -67,4 +69,5 @@ def test_committed_cache_is_well_formed():
         prec, bp, mx, nt = key.split("/")
         assert prec in ("fp32", "fp64") and bp.startswith("bp") and mx.startswith("mx") and nt.startswith("nt")
         assert set(e["tuning"]) <= set(autotune.FIELDS)
-        assert e["tuning"]["gemm_tile_m_fp32"] in (64, 128) and e["tuning"]["gemm_tile_m_fp64"] in (64, 128)
+        assert e["tuning"]["gemm_tile_m_fp32"] in (64, 128)
+        assert (e["tuning"]["gemm_tile_m_fp64"], e["tuning"].get("gemm_tile_n_fp64", 64)) in autotune.FP64_TILES

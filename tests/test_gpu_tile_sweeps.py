@@ -161,16 +161,19 @@ def test_tuning_rejects_negative():
         prob.set_tuning(gemm_tile_m_fp64=96)
     with pytest.raises(stfd.StfdError):
         prob.set_tuning(gemm_n_fast=2)
+    with pytest.raises(stfd.StfdError):
+        prob.set_tuning(gemm_tile_m_fp64=64, gemm_tile_n_fp64=128)   # 128 columns need 128 rows
     with pytest.raises(ValueError):
         prob.set_tuning(no_such_field=1)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_gemm_variants_give_the_same_solution(precision):
-    """The GEMM tile height (64 or 128 rows) and grid order change only
-    which workgroup computes an output entry, not the order of its sum over
-    K: the refined solution is bit-identical for every variant, with a ragged
-    M (M_x = 1225, not a multiple of 64 or 128)."""
+    """The GEMM tile (64 x 64, 128 x 64, 128 x 128 on FP64 matrix cores) and
+    grid order change only which workgroup computes an output entry, not the
+    order of its sum over K: the refined solution is bit-identical for every
+    variant, with a ragged M (M_x = 1225, not a multiple of 64 or 128) and
+    ragged N and K (2 n_sys = 22)."""
     mesh = w.square_mesh(36)
     t = w.uniform_times(20)
     At, Mt, Ct = tm.kernel(t)
@@ -179,9 +182,10 @@ def test_gemm_variants_give_the_same_solution(precision):
     F = torch.from_numpy(np.ascontiguousarray(np.stack([f.T for f in Fs]))).to("cuda:0")
     sp = stfd.Space(mesh)
     ref = None
-    for bm32, bm64, nfast in ((64, 64, 0), (128, 64, 0), (64, 128, 1), (128, 128, 1)):
+    for bm32, bm64, bn64, nfast in ((64, 64, 64, 0), (128, 64, 64, 0), (64, 128, 64, 1), (128, 128, 64, 1),
+                                    (64, 128, 128, 0), (128, 128, 128, 1)):
         prob = stfd.Problem(sp, At, Mt, precision=precision, rtol=1e-11)
-        prob.set_tuning(gemm_tile_m_fp32=bm32, gemm_tile_m_fp64=bm64, gemm_n_fast=nfast)
+        prob.set_tuning(gemm_tile_m_fp32=bm32, gemm_tile_m_fp64=bm64, gemm_tile_n_fp64=bn64, gemm_n_fast=nfast)
         prob.factor()
         U = torch.empty_like(F)
         prob.solve(F, U)
@@ -192,4 +196,4 @@ def test_gemm_variants_give_the_same_solution(precision):
                 Uo = so.direct(At, Mt, Mx, Ax, Fs[q])
                 assert np.linalg.norm(U[q].cpu().numpy().T - Uo) / np.linalg.norm(Uo) <= 1e-10
         else:
-            assert torch.equal(U, ref), (bm32, bm64, nfast)
+            assert torch.equal(U, ref), (bm32, bm64, bn64, nfast)
