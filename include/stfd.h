@@ -301,6 +301,16 @@ int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* rep);
  *                       systems on 2 p + 1 workgroups; 0: one complex
  *                       workgroup each.  The factors are the same bit for
  *                       bit.  The other kernels ignore it.
+ *   sweep_pack_real     1 (default): inside an FD application the tile
+ *                       sweeps take Alg. FD's real systems two to a
+ *                       workgroup, one in the real and one in the imaginary
+ *                       slot of the complex arithmetic (their imaginary
+ *                       parts, zero up to the rounding of the forward
+ *                       transform, are written as zeros; the back transform
+ *                       weighs them with zeros, so U is the same bit for
+ *                       bit); 0: one complex workgroup each.
+ *                       stfd_spatial_solve always solves every system in
+ *                       full.
  * stfd_set_tuning takes effect from the next stfd_fd_factor (the tile
  * sweeps need the inverses of the diagonal blocks, formed by the factor).
  * Errors: STFD_EINVAL (null pointers, a value out of range).  Host only.
@@ -313,6 +323,7 @@ typedef struct {
     int factor_kernel;
     int factor_pack_real;
     int gemm_tile_n_fp64;
+    int sweep_pack_real;
 } stfd_tuning;
 
 int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t);

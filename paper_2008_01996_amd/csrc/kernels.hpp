@@ -111,10 +111,10 @@ template <typename T>
 // reach[b]: 16-row blocks below diagonal block b that the factor's columns
 // reach (the envelope; blocks beyond are zero and skipped)
 hipError_t launch_tile_forward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
-                               const void* G, void* W, hipStream_t st, int sys0, int nrun);
+                               const void* G, void* W, hipStream_t st, int sys0, int nrun, int nreal);
 template <typename T>
 hipError_t launch_tile_backward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
-                                void* W, hipStream_t st, int sys0, int nrun);
+                                void* W, hipStream_t st, int sys0, int nrun, int nreal);
 template <typename T>
 size_t band_ldl_smem(int bp);
 template <typename T>

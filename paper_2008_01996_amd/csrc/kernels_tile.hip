@@ -98,20 +98,23 @@ __global__ void __launch_bounds__(128) band_diag_inverse_kernel(const cplx<T>* _
 // The tile sweep.  S slots per wave (ceil(NB / 4)), NSET register sets of
 // prefetched factor operands.
 // ---------------------------------------------------------------------------
-template <typename T, bool FWD, int S, int NSET>
-__global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restrict__ LB,
-                                                        const cplx<T>* __restrict__ LI, int Mx, int bp, int nsys,
-                                                        int nrhs, const T* __restrict__ Vin, T* __restrict__ Vout,
-                                                        int sys0, const int* __restrict__ reach,
-                                                        const int* __restrict__ gate) {
-    if (gate && *gate) return;
+// PAIR: two real systems A and B (lambda real, factors and right-hand sides
+// real: the imaginary parts of real systems are zero, up to the rounding of
+// the forward transform, and do not reach U, since the back transform weighs
+// them with the zero imaginary parts of their real eigenvectors) carried in
+// the real and imaginary slots of one complex sweep: every operand's real
+// part is A's, its imaginary part B's, and the products drop the cross
+// terms.  Both imaginary parts of the result are written as zeros.
+template <typename T, bool FWD, int S, int NSET, bool PAIR>
+__device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, const cplx<T>* __restrict__ LI,
+                                                int Mx, int bp, int nsys, int nrhs, const T* __restrict__ Vin,
+                                                T* __restrict__ Vout, int sys, int sysB,
+                                                const int* __restrict__ reach, T (*XR)[TB][XS], T (*XI)[TB][XS],
+                                                T (*YR)[TB][XS], T (*YI)[TB][XS]) {
     using V4 = typename vec4<T>::type;
-    __shared__ T XR[NWAVE][TB][XS], XI[NWAVE][TB][XS];    // owner's tile in operand layout
-    __shared__ T YR[2][TB][XS], YI[2][TB][XS];            // solved block, by step parity
     const int bp1 = bp + 1;
     const int NB = bp / TB;
     const int nblk = (Mx + TB - 1) / TB;
-    const int sys = sys0 + blockIdx.x;
     const int r0 = blockIdx.y * TB;
     const int nr = min(TB, nrhs - r0);
     const int tid = threadIdx.x;
@@ -121,12 +124,20 @@ __global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restri
     const bool nlive = n < nr;
     const size_t rstride = (size_t)Mx * 2 * nsys;
     const size_t voff = (size_t)(r0 + (nlive ? n : 0)) * rstride;
+    // (PAIR: the "imaginary" input and output are B's real parts)
     const T* vin_re = Vin + voff + (size_t)sys * Mx;
-    const T* vin_im = Vin + voff + (size_t)(nsys + sys) * Mx;
+    const T* vin_im = Vin + voff + (size_t)(PAIR ? sysB : nsys + sys) * Mx;
     T* vout_re = Vout + voff + (size_t)sys * Mx;
-    T* vout_im = Vout + voff + (size_t)(nsys + sys) * Mx;
+    T* vout_im = Vout + voff + (size_t)(PAIR ? sysB : nsys + sys) * Mx;
     const cplx<T>* base = LB + (size_t)sys * Mx * bp1;
     const cplx<T>* libase = LI + (size_t)sys * nblk * TB * TB;
+    const cplx<T>* baseB = LB + (size_t)sysB * Mx * bp1;
+    const cplx<T>* libaseB = LI + (size_t)sysB * nblk * TB * TB;
+    // an operand's imaginary slot: B's real part of the same entry
+    auto im_of = [&](const cplx<T>* e, const cplx<T>* a, const cplx<T>* b) -> T {
+        if constexpr (PAIR) return b[e - a].re;
+        else return e->im;
+    };
 
     // tile of the input vector for block j, accumulator layout.  The loads
     // are issued raw (address clamped) so that they stay in flight;
@@ -218,21 +229,21 @@ __global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restri
             for (int kk = 0; kk < 4; ++kk) {
                 const cplx<T>* e = base + q_index(j, c, kk);
                 qx[t][kk].re = e->re;                 // raw: masked where used
-                qx[t][kk].im = e->im;
+                qx[t][kk].im = im_of(e, base, baseB);
             }
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
             const cplx<T>* e = libase + li_addr(c, kk);
             px[kk].re = e->re;
-            px[kk].im = e->im;
+            px[kk].im = im_of(e, libase, libaseB);
         }
         load_tile_raw(FWD ? c + 4 * S : c - 4 * S, ex[0], ex[1]);
         if (FWD) {
             const int row = min(max(TB * c + 4 * w + g, 0), Mx - 1);
             const cplx<T>* e = base + (size_t)row * bp1;
             dx.re = e->re;
-            dx.im = e->im;
+            dx.im = im_of(e, base, baseB);
         }
     };
 #pragma unroll
@@ -256,10 +267,15 @@ __global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restri
                 for (int kk = 0; kk < 4; ++kk) {
                     const T br = XR[w][4 * kk + g][n], bi = XI[w][4 * kk + g][n];
                     const cplx<T> a = px[kk];
-                    xr = mfma16x16x4<T>(a.re, br, xr);
-                    xr = mfma16x16x4<T>(-a.im, bi, xr);
-                    xi = mfma16x16x4<T>(a.re, bi, xi);
-                    xi = mfma16x16x4<T>(a.im, br, xi);
+                    if constexpr (PAIR) {
+                        xr = mfma16x16x4<T>(a.re, br, xr);
+                        xi = mfma16x16x4<T>(a.im, bi, xi);
+                    } else {
+                        xr = mfma16x16x4<T>(a.re, br, xr);
+                        xr = mfma16x16x4<T>(-a.im, bi, xr);
+                        xi = mfma16x16x4<T>(a.re, bi, xi);
+                        xi = mfma16x16x4<T>(a.im, br, xi);
+                    }
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -284,13 +300,23 @@ __global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restri
                 const int rl = 4 * w + g, row = TB * c + rl;
                 T vr = YR[par][rl][n], vi = YI[par][rl][n];
                 if (FWD) {
-                    const cplx<T> o = cmul(cplx<T>{vr, vi}, cinv_fast(dx));
-                    vr = o.re;
-                    vi = o.im;
+                    if constexpr (PAIR) {
+                        vr = vr * cinv_fast(cplx<T>{dx.re, T(0)}).re;
+                        vi = vi * cinv_fast(cplx<T>{dx.im, T(0)}).re;
+                    } else {
+                        const cplx<T> o = cmul(cplx<T>{vr, vi}, cinv_fast(dx));
+                        vr = o.re;
+                        vi = o.im;
+                    }
                 }
                 if (nlive && row < Mx) {
                     vout_re[row] = vr;
                     vout_im[row] = vi;
+                    if constexpr (PAIR) {
+                        // the imaginary parts of both real systems
+                        Vout[voff + (size_t)(nsys + sys) * Mx + row] = T(0);
+                        Vout[voff + (size_t)(nsys + sysB) * Mx + row] = T(0);
+                    }
                 }
             }
             const int delta = FWD ? ((w - c - 1) & 3) + 1 : ((c - w - 1) & 3) + 1;
@@ -318,10 +344,15 @@ __global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restri
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         const cplx<T> a = qx[t][kk];
-                        accR[t] = mfma16x16x4<T>(-a.re, br[kk], accR[t]);
-                        accR[t] = mfma16x16x4<T>(a.im, bi[kk], accR[t]);
-                        accI[t] = mfma16x16x4<T>(-a.re, bi[kk], accI[t]);
-                        accI[t] = mfma16x16x4<T>(-a.im, br[kk], accI[t]);
+                        if constexpr (PAIR) {
+                            accR[t] = mfma16x16x4<T>(-a.re, br[kk], accR[t]);
+                            accI[t] = mfma16x16x4<T>(-a.im, bi[kk], accI[t]);
+                        } else {
+                            accR[t] = mfma16x16x4<T>(-a.re, br[kk], accR[t]);
+                            accR[t] = mfma16x16x4<T>(a.im, bi[kk], accR[t]);
+                            accI[t] = mfma16x16x4<T>(-a.re, bi[kk], accI[t]);
+                            accI[t] = mfma16x16x4<T>(-a.im, br[kk], accI[t]);
+                        }
                     }
                 }
             }
@@ -332,6 +363,30 @@ __global__ void __launch_bounds__(256) tile_sweep_kernel(const cplx<T>* __restri
     for (int s0 = 0; s0 < nblk; s0 += NSET) {
 #pragma unroll
         for (int u = 0; u < NSET; ++u) step(s0 + u, qa[u], pa[u], da[u], ea[u]);
+    }
+}
+
+// Workgroups [0, ncplx): system sys0 + x, complex; workgroups past ncplx:
+// the real systems sys0 + ncplx + 2 (x - ncplx) and the next one (if any, else
+// the same system twice, its results written by both slots alike), paired.
+template <typename T, bool FWD, int S, int NSET>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) tile_sweep_kernel(const cplx<T>* __restrict__ LB,
+                                                        const cplx<T>* __restrict__ LI, int Mx, int bp, int nsys,
+                                                        int nrhs, const T* __restrict__ Vin, T* __restrict__ Vout,
+                                                        int sys0, int ncplx, int nrun,
+                                                        const int* __restrict__ reach,
+                                                        const int* __restrict__ gate) {
+    if (gate && *gate) return;
+    __shared__ T XR[NWAVE][TB][XS], XI[NWAVE][TB][XS];    // owner's tile in operand layout
+    __shared__ T YR[2][TB][XS], YI[2][TB][XS];            // solved block, by step parity
+    const int x = blockIdx.x;
+    if (x < ncplx) {
+        tile_sweep_body<T, FWD, S, NSET, false>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, sys0 + x, sys0 + x, reach,
+                                                XR, XI, YR, YI);
+    } else {
+        const int a = sys0 + ncplx + 2 * (x - ncplx);
+        const int b = a + 1 < sys0 + nrun ? a + 1 : a;
+        tile_sweep_body<T, FWD, S, NSET, true>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, a, b, reach, XR, XI, YR, YI);
     }
 }
 
@@ -350,50 +405,52 @@ hipError_t launch_band_diag_inverse(const void* LB, void* LI, int Mx, int bp, in
 
 template <typename T, bool FWD, int S>
 static hipError_t launch_tile_t(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
-                                const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun) {
+                                const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun, int nreal) {
     constexpr int NSET = sizeof(T) == 4 ? 3 : 2;     // prefetch distance in steps
-    dim3 grid(nrun, (nrhs + TB - 1) / TB);
+    const int ncplx = nrun - nreal;
+    dim3 grid(ncplx + (nreal + 1) / 2, (nrhs + TB - 1) / TB);
     hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET>), grid, dim3(256), 0, st,
                        static_cast<const cplx<T>*>(LB), static_cast<const cplx<T>*>(LI), Mx, bp, nsys, nrhs,
-                       static_cast<const T*>(Vin), static_cast<T*>(Vout), sys0, reach, launch_gate());
+                       static_cast<const T*>(Vin), static_cast<T*>(Vout), sys0, ncplx, nrun, reach, launch_gate());
     return hipGetLastError();
 }
 
 template <typename T, bool FWD>
 static hipError_t launch_tile(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
-                              const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun) {
-    if (bp < TB || bp % TB != 0 || bp > TILE_BPMAX || sys0 < 0 || nrun < 1 || sys0 + nrun > nsys || nrhs < 1)
+                              const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun, int nreal) {
+    if (bp < TB || bp % TB != 0 || bp > TILE_BPMAX || sys0 < 0 || nrun < 1 || sys0 + nrun > nsys || nrhs < 1 ||
+        nreal < 0 || nreal > nrun)
         return hipErrorInvalidValue;
     const int slots = (bp / TB + 3) / 4;
     switch (slots) {
-        case 1: return launch_tile_t<T, FWD, 1>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
-        case 2: return launch_tile_t<T, FWD, 2>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
-        case 3: return launch_tile_t<T, FWD, 3>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
-        default: return launch_tile_t<T, FWD, 4>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun);
+        case 1: return launch_tile_t<T, FWD, 1>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun, nreal);
+        case 2: return launch_tile_t<T, FWD, 2>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun, nreal);
+        case 3: return launch_tile_t<T, FWD, 3>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun, nreal);
+        default: return launch_tile_t<T, FWD, 4>(LB, LI, reach, Mx, bp, nsys, nrhs, Vin, Vout, st, sys0, nrun, nreal);
     }
 }
 
 template <typename T>
 hipError_t launch_tile_forward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
-                               const void* G, void* W, hipStream_t st, int sys0, int nrun) {
-    return launch_tile<T, true>(LB, LI, reach, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun);
+                               const void* G, void* W, hipStream_t st, int sys0, int nrun, int nreal) {
+    return launch_tile<T, true>(LB, LI, reach, Mx, bp, nsys, nrhs, G, W, st, sys0, nrun, nreal);
 }
 
 template <typename T>
 hipError_t launch_tile_backward(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
-                                void* W, hipStream_t st, int sys0, int nrun) {
-    return launch_tile<T, false>(LB, LI, reach, Mx, bp, nsys, nrhs, W, W, st, sys0, nrun);
+                                void* W, hipStream_t st, int sys0, int nrun, int nreal) {
+    return launch_tile<T, false>(LB, LI, reach, Mx, bp, nsys, nrhs, W, W, st, sys0, nrun, nreal);
 }
 
 template hipError_t launch_band_diag_inverse<float>(const void*, void*, int, int, int, hipStream_t);
 template hipError_t launch_band_diag_inverse<double>(const void*, void*, int, int, int, hipStream_t);
 template hipError_t launch_tile_forward<float>(const void*, const void*, const int*, int, int, int, int, const void*,
-                                               void*, hipStream_t, int, int);
+                                               void*, hipStream_t, int, int, int);
 template hipError_t launch_tile_forward<double>(const void*, const void*, const int*, int, int, int, int, const void*,
-                                                void*, hipStream_t, int, int);
+                                                void*, hipStream_t, int, int, int);
 template hipError_t launch_tile_backward<float>(const void*, const void*, const int*, int, int, int, int, void*,
-                                                hipStream_t, int, int);
+                                                hipStream_t, int, int, int);
 template hipError_t launch_tile_backward<double>(const void*, const void*, const int*, int, int, int, int, void*,
-                                                 hipStream_t, int, int);
+                                                 hipStream_t, int, int, int);
 
 }  // namespace stfd

@@ -42,6 +42,7 @@ struct stfd_problem {
     int gemm_nfast = 0;         // GEMM grid order
     int factor_kernel = 0;      // band factor kernel (stfd_tuning.factor_kernel)
     int factor_pack_real = 1;   // real systems two to a workgroup (stfd_tuning.factor_pack_real)
+    int sweep_pack_real = 1;    // the same for the tile sweeps (stfd_tuning.sweep_pack_real)
     int* d_flag = nullptr;
     // work buffers, sized for nrhs_cap right-hand sides
     int nrhs_cap = 0;

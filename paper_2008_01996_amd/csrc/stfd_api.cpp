@@ -718,6 +718,7 @@ extern "C" int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t) {
     t->gemm_n_fast = p->gemm_nfast;
     t->factor_kernel = p->factor_kernel;
     t->factor_pack_real = p->factor_pack_real;
+    t->sweep_pack_real = p->sweep_pack_real;
     return STFD_OK;
 }
 
@@ -726,6 +727,7 @@ extern "C" int stfd_set_tuning(stfd_problem* p, const stfd_tuning* t) {
     if (!p || !t || t->sweep_tile_min_rhs < 0 || !tile_ok(t->gemm_tile_m_fp32) || !tile_ok(t->gemm_tile_m_fp64) ||
         (t->gemm_n_fast != 0 && t->gemm_n_fast != 1) || t->factor_kernel < 0 || t->factor_kernel > 2 ||
         (t->factor_pack_real != 0 && t->factor_pack_real != 1) ||
+        (t->sweep_pack_real != 0 && t->sweep_pack_real != 1) ||
         (t->gemm_tile_n_fp64 != 64 && !(t->gemm_tile_n_fp64 == 128 && t->gemm_tile_m_fp64 == 128)))
         return fail(STFD_EINVAL, "set_tuning: bad arguments");
     drop_graphs(p);                     // captured rounds hold the old kernel choice
@@ -735,6 +737,7 @@ extern "C" int stfd_set_tuning(stfd_problem* p, const stfd_tuning* t) {
     p->gemm_nfast = t->gemm_n_fast;
     p->factor_kernel = t->factor_kernel;
     p->factor_pack_real = t->factor_pack_real;
+    p->sweep_pack_real = t->sweep_pack_real;
     p->tile_min_rhs = p->bp <= stfd::TILE_BPMAX ? t->sweep_tile_min_rhs : 0;
     if (p->tile_min_rhs == 0) {
         (void)hipFree(p->d_LI);
@@ -785,23 +788,29 @@ extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
 
 namespace {
 
-int spatial_sweeps(stfd_problem* p, int nrhs, const void* G, void* Z, hipStream_t st) {
+// pack_real: inside an FD application, where the imaginary parts of the
+// real systems do not reach U, the tile sweeps may take those systems in
+// pairs (and write their imaginary parts as zeros); stfd_spatial_solve
+// solves every system in full
+int spatial_sweeps(stfd_problem* p, int nrhs, const void* G, void* Z, hipStream_t st, bool pack_real) {
     const bool f32 = is_fp32(p);
     if (p->d_LI && nrhs >= p->tile_min_rhs) {
+        // FD's real systems (ordered last) two to a workgroup
+        const int nreal = pack_real && p->method == STFD_METHOD_FD && p->sweep_pack_real ? p->nreal : 0;
         {
             StageTimer tm(p, STFD_ST_SWEEP_FWD, st);
-            HIPCHK(f32 ? stfd::launch_tile_forward<float>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0,
-                                                          p->nsys)
-                       : stfd::launch_tile_forward<double>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, G, Z, st, 0,
-                                                           p->nsys),
+            HIPCHK(f32 ? stfd::launch_tile_forward<float>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, G, Z,
+                                                          st, 0, p->nsys, nreal)
+                       : stfd::launch_tile_forward<double>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, G, Z,
+                                                           st, 0, p->nsys, nreal),
                    "forward tile sweep");
         }
         {
             StageTimer tm(p, STFD_ST_SWEEP_BWD, st);
-            HIPCHK(f32 ? stfd::launch_tile_backward<float>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, Z, st, 0,
-                                                           p->nsys)
-                       : stfd::launch_tile_backward<double>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, Z, st, 0,
-                                                            p->nsys),
+            HIPCHK(f32 ? stfd::launch_tile_backward<float>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, Z, st,
+                                                           0, p->nsys, nreal)
+                       : stfd::launch_tile_backward<double>(p->d_LB, p->d_LI, p->d_reach, p->Mx, p->bp, p->nsys, nrhs, Z,
+                                                            st, 0, p->nsys, nreal),
                    "backward tile sweep");
         }
         return STFD_OK;
@@ -898,7 +907,7 @@ int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
     // step 3: spatial solves, in place in G (with the inner refinement: G
     // kept in Gs, Z into G; then Gs -= S_k Z in FP64, solved in place, and
     // the correction added to Z)
-    int rc = spatial_sweeps(p, nrhs, inner ? p->d_Gs : p->d_G, p->d_G, st);
+    int rc = spatial_sweeps(p, nrhs, inner ? p->d_Gs : p->d_G, p->d_G, st, true);
     if (rc) return rc;
     if (inner) {
         {
@@ -909,7 +918,7 @@ int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
                                                             p->d_valA, p->d_lam, p->d_Gs, p->d_G, st),
                    "inner residual");
         }
-        rc = spatial_sweeps(p, nrhs, p->d_Gs, p->d_Gs, st);
+        rc = spatial_sweeps(p, nrhs, p->d_Gs, p->d_Gs, st, true);
         if (rc) return rc;
         {
             StageTimer tm(p, STFD_ST_INNER, st);
@@ -1051,7 +1060,7 @@ extern "C" int stfd_spatial_solve(stfd_problem* p, int nrhs, const void* G_dev, 
     if (!p || nrhs < 1 || !G_dev || !Z_dev) return fail(STFD_EINVAL, "spatial_solve: bad arguments");
     if (!p->factored) return fail(STFD_ESTATE, "spatial_solve: call stfd_fd_factor first");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    int rc = spatial_sweeps(p, nrhs, G_dev, Z_dev, st);
+    int rc = spatial_sweeps(p, nrhs, G_dev, Z_dev, st, false);
     if (rc) return rc;
     stfd::clear_error();
     return STFD_OK;

@@ -49,7 +49,7 @@ class Opts(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("sweep_tile_min_rhs", C.c_int), ("gemm_tile_m_fp32", C.c_int), ("gemm_tile_m_fp64", C.c_int),
                 ("gemm_n_fast", C.c_int), ("factor_kernel", C.c_int), ("factor_pack_real", C.c_int),
-                ("gemm_tile_n_fp64", C.c_int)]
+                ("gemm_tile_n_fp64", C.c_int), ("sweep_pack_real", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -197,3 +197,40 @@ def test_gemm_variants_give_the_same_solution(precision):
                 assert np.linalg.norm(U[q].cpu().numpy().T - Uo) / np.linalg.norm(Uo) <= 1e-10
         else:
             assert torch.equal(U, ref), (bm32, bm64, bn64, nfast)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("nt", [12, 11])
+def test_real_system_pairs_give_the_same_solution(precision, nt):
+    """Inside an FD application the tile sweeps take the real systems two to
+    a workgroup (one in the real, one in the imaginary slot;
+    sweep_pack_real = 1) or one complex workgroup each: the refined solution
+    U is the same bit for bit (the real parts of those systems' solutions
+    are computed alike, their imaginary parts reach U only weighted by
+    zeros), for an even and an odd number of real systems; the
+    application count and the residual history agree too."""
+    mesh = w.lshape_mesh(10)
+    t = w.graded_times(nt)
+    At, Mt, Ct = tm.kernel(t)
+    Mx, Ax, M10 = sm.assemble(mesh)
+    Fs = [load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(8800 + r)), Ct) for r in range(3)]
+    F = torch.from_numpy(np.ascontiguousarray(np.stack([f.T for f in Fs]))).to("cuda:0")
+    sp = stfd.Space(mesh)
+    out = {}
+    for pack in (0, 1):
+        prob = stfd.Problem(sp, At, Mt, precision=precision, rtol=1e-11, tuning=None)
+        prob.set_tuning(sweep_tile_min_rhs=1, sweep_pack_real=pack)
+        prob.factor()
+        n, nreal = prob.setup_report["n_sys"], prob.setup_report["n_real"]
+        assert nreal >= 1
+        U = torch.empty_like(F)
+        rep = prob.solve(F, U)
+        torch.cuda.synchronize()
+        out[pack] = (U, rep)
+    assert torch.equal(out[1][0], out[0][0])
+    assert out[1][1]["iterations"] == out[0][1]["iterations"]
+    assert out[1][1]["rel_residual"] == out[0][1]["rel_residual"]
+    for q in range(3):
+        Uo = so.direct(At, Mt, Mx, Ax, Fs[q])
+        assert np.linalg.norm(out[1][0][q].cpu().numpy().T - Uo) / np.linalg.norm(Uo) <= 1e-10
+    print(f"  N_t {nt}: {n} systems, {nreal} real: paired sweeps give the same U", flush=True)
