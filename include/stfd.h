@@ -290,10 +290,13 @@ int stfd_fd_setup_report(const stfd_problem* p, stfd_setup_report* rep);
  *   factor_kernel       the band LDL^T (step 3 of Alg. FD, first half):
  *                       0 = automatic (register window for FP32 with padded
  *                       half-bandwidth 128, LDS window where it fits, else
- *                       the panel kernel), 1 = trailing tiles streamed with
+ *                       the panel kernel 3 in FP32 and 2 in FP64), 1 =
+ *                       trailing tiles streamed with
  *                       the panel factored in LDS, 2 = panel factored in
  *                       registers with the trailing tiles streamed and the
- *                       next panel handed over on chip.
+ *                       next panel handed over on chip, 3 = the same with two
+ *                       16-column panels per pass, the trailing tiles taking
+ *                       both panels' update at once (FP32 only).
  *   factor_pack_real    1 (default): the panel kernel (2, and the automatic
  *                       choice where it takes that kernel) factors the real
  *                       systems of Alg. FD (real lambda, ordered last) two

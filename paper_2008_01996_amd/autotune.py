@@ -176,7 +176,7 @@ def tune_problem(prob, F, reps: int = 3, rhs_counts=RHS_COUNTS, log=print) -> di
     factor_kernel = 0
     if not window:
         fms = {}
-        for fk in (1, 2):
+        for fk in ((1, 2, 3) if prob.precision == "fp32" else (1, 2)):
             prob.set_tuning(**{**base, "factor_kernel": fk})
             fms[fk] = _time(prob.factor, reps)
             log(f"  factor kernel {fk}: {fms[fk]:.2f} ms")

@@ -80,10 +80,11 @@ template <typename T>
 hipError_t launch_band_init(void* LB, int Mx, int bp, int nsys, const int* rowptr, const int* col,
                             const double* valM, const double* valA, const double* lam, hipStream_t st);
 // factor kernel: automatic (the register window for FP32 with padded band
-// 128, the LDS window where it fits, else the panel kernel), or forced.  The
+// 128, the LDS window where it fits, else the panel kernel: two panels per
+// pass in FP32, one in FP64), or forced.  The
 // last nreal systems are real (every imaginary part zero): the panel kernel
 // factors them two to a workgroup in real arithmetic.
-enum { FACTOR_AUTO = 0, FACTOR_STREAM = 1, FACTOR_PANEL = 2 };
+enum { FACTOR_AUTO = 0, FACTOR_STREAM = 1, FACTOR_PANEL = 2, FACTOR_PANEL2 = 3 };
 template <typename T>
 hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int nreal, const int* reach, int* flag, int kernel,
                            hipStream_t st);

@@ -917,6 +917,309 @@ __global__ void __launch_bounds__(512) band_ldl_panel_kernel(cplx<T>* __restrict
 }
 
 // ---------------------------------------------------------------------------
+// Bands up to 256 with two 16-column panels per pass (FP32): the trailing
+// tiles take the update of both panels, 32 terms, for one read and one write,
+// half the tile traffic of the kernel above.  Pass Q (blocks b0 = 2Q and
+// b1 = 2Q + 1, columns p0 = 32 Q .. p0 + 31, p1 = p0 + 16):
+//  1. panel 0 (block b0) is factored in registers as above (its rows from
+//     the hand-over NX0 or HBM), written out, its rows below the diagonal
+//     block and D to LDS (PL0, PD0);
+//  2. panel 1's column (block b1, rows of its band) sits in LDS (NX1: handed
+//     over by the previous pass, the rest loaded from HBM a step ahead) and
+//     takes panel 0's update there (tiles on the matrix cores);
+//  3. panel 1 is factored in registers from NX1, written out, PL1 and PD1 to
+//     LDS;
+//  4. the trailing tiles right of block b1 take both panels' update, summed
+//     on their own and subtracted once: C -= L0 D0 L0^T + L1 D1 L1^T; the
+//     tiles of blocks b0 + 2 and b0 + 3 (the next pass's panels) go to NX0
+//     and NX1 instead of HBM.
+// LDS (complex, stride PS): PL0 [272], PL1 [256], NX0 [256], NX1 [272] rows,
+// PD0 and PD1: 138.4 KB in FP32.
+// ---------------------------------------------------------------------------
+constexpr int P2_ROWS0 = 272, P2_ROWS1 = 256, P2_NX0 = 256, P2_NX1 = 272;
+
+template <typename T>
+static size_t panel2_smem() {
+    return ((size_t)(P2_ROWS0 + P2_ROWS1 + P2_NX0 + P2_NX1) * PS + 32) * sizeof(cplx<T>);
+}
+
+template <typename T, bool REAL>
+__device__ __forceinline__ void panel2_factor_system(cplx<T>* __restrict__ base, int Mx, int bp,
+                                                     const int* __restrict__ reach, int* __restrict__ flag,
+                                                     unsigned char* smem_raw) {
+    using V4 = typename vec4<T>::type;
+    cplx<T>* PL0 = reinterpret_cast<cplx<T>*>(smem_raw);  // panel 0's L rows below its diagonal block (row p1 + r)
+    cplx<T>* PL1 = PL0 + P2_ROWS0 * PS;                   // panel 1's L rows below its diagonal block (p1 + 16 + r)
+    cplx<T>* NX0 = PL1 + P2_ROWS1 * PS;                   // hand-over: the next panel 0's rows (p0 + r)
+    cplx<T>* NX1 = NX0 + P2_NX0 * PS;                     // panel 1's column (p1 + r)
+    cplx<T>* PD0 = NX1 + P2_NX1 * PS;
+    cplx<T>* PD1 = PD0 + 16;
+    using V2 = T __attribute__((ext_vector_type(2)));
+    using LdsV2 = __attribute__((address_space(3))) V2;
+    using GlbV2 = __attribute__((address_space(1))) V2;
+    LdsV2* NX0s = (LdsV2*)NX0;
+    LdsV2* NX1s = (LdsV2*)NX1;
+    GlbV2* gbase = (GlbV2*)base;
+    const int bp1 = bp + 1;
+    const int NB = bp / 16;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lk = lane >> 4;
+    const int nblk = (Mx + 15) / 16;
+    const bool own = lane < 48;
+    const int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
+
+    auto ent_on = [&](int p0, int c, int nrow) {
+        const int d = rrel - c;
+        return own && rrel < nrow && d >= 0 && d <= bp && p0 + rrel < Mx && p0 + c < Mx;
+    };
+    auto ent_off = [&](int p0, int c, int nrow, int lo) -> int {
+        return ent_on(p0, c, nrow) && rrel >= lo ? (p0 + c) * bp1 + (rrel - c) : 0;
+    };
+    cplx<T> pf[16];
+    auto prefetch = [&](int p0, int nrow, int lo) {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+            const cplx<T>* e = base + ent_off(p0, c, nrow, lo);
+            pf[c].re = e->re;
+            pf[c].im = e->im;
+        }
+    };
+    // factor the 16 columns of this lane's panel row in registers (lane
+    // broadcasts, no barrier); returns the bad-pivot flag
+    auto factor_row = [&](cplx<T> (&a)[16], int nb) {
+        int bad = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k < nb) {
+                const cplx<T> dk = {lane_bcast(a[k].re, k), lane_bcast(a[k].im, k)};
+                const cplx<T> inv = cinv_fast(dk);
+                const T mag = fabs(dk.re) + fabs(dk.im);
+                bad |= int(!(mag > T(0))) | int(!isfinite(mag));
+                const cplx<T> aik = a[k];
+                if constexpr (REAL) {
+                    if (rrel > k) a[k].re = aik.re * inv.re;
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) a[j].re = fma(-aik.re, lane_bcast(a[k].re, j), a[j].re);
+                } else {
+                    if (rrel > k) a[k] = cmul(aik, inv);
+#pragma unroll
+                    for (int j = k + 1; j < 16; ++j) {
+                        const T lr = lane_bcast(a[k].re, j), lim = lane_bcast(a[k].im, j);
+                        a[j].re = fma(-aik.re, lr, a[j].re);
+                        a[j].re = fma(aik.im, lim, a[j].re);
+                        a[j].im = fma(-aik.re, lim, a[j].im);
+                        a[j].im = fma(-aik.im, lr, a[j].im);
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        return bad;
+    };
+    // write a factored panel out, its L rows (zero past nrow) to PL and D to PD
+    auto panel_out = [&](const cplx<T> (&a)[16], int p0, int nb, int nrow, cplx<T>* PL, cplx<T>* PD) {
+        const bool writer = own && (lane >= 16 || wave == 0);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (writer && c < nb && ent_on(p0, c, nrow)) base[(p0 + c) * bp1 + (rrel - c)] = a[c];
+        if (own && lane >= 16) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const bool in = rrel < nrow;
+                PL[(rrel - 16) * PS + c] = cplx<T>{in ? a[c].re : T(0), in ? a[c].im : T(0)};
+            }
+        }
+        cplx<T> dg = a[0];
+#pragma unroll
+        for (int c = 1; c < 16; ++c) {
+            dg.re = lane == c ? a[c].re : dg.re;
+            dg.im = lane == c ? a[c].im : dg.im;
+        }
+        if (wave == 0 && lane < 16) PD[lane] = dg;
+    };
+    auto tile_ij = [](int t, int& ti, int& tj) {
+        ti = 0;
+        while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+        tj = t - ti * (ti + 1) / 2;
+    };
+    // this lane's share of a tile update: u = sum_k x_k (y_k d_k) over the
+    // panel's 16 columns (x: column-side rows, y: row-side rows of PL)
+    auto tile_sum = [&](V4& ur, V4& ui, const cplx<T>* PL, const cplx<T>* PD, int xrow, int yrow) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int k = 4 * kk + lk;
+            if constexpr (REAL) {
+                ur = mfma16x16x4<T>(PL[(xrow + li) * PS + k].re, PL[(yrow + li) * PS + k].re * PD[k].re, ur);
+            } else {
+                const cplx<T> x = PL[(xrow + li) * PS + k];
+                const cplx<T> y = cmul(PL[(yrow + li) * PS + k], PD[k]);
+                ur = mfma16x16x4<T>(x.re, y.re, ur);
+                ui = mfma16x16x4<T>(x.re, y.im, ui);
+                ur = mfma16x16x4<T>(-x.im, y.im, ur);
+                ui = mfma16x16x4<T>(x.im, y.re, ui);
+            }
+        }
+    };
+
+    // PL0 rows 256 .. 271 (row p1 + 256 and below: never inside panel 0's
+    // band) stay zero
+    for (int e = tid; e < (P2_ROWS0 - 256) * PS; e += blockDim.x) PL0[256 * PS + e] = cplx<T>{T(0), T(0)};
+    int nx0 = 0, nx1 = 0;                                 // rows of NX0 / NX1 handed over
+    prefetch(0, nblk > 0 ? 16 + 16 * min(NB, reach[0]) : 0, 0);
+
+    for (int b0 = 0; b0 < nblk; b0 += 2) {
+        const int b1 = b0 + 1;
+        const bool has1 = b1 < nblk;
+        const int p0 = 16 * b0, p1 = p0 + 16;
+        const int nb0 = min(16, Mx - p0), nb1 = has1 ? min(16, Mx - p1) : 0;
+        const int nr0 = min(NB, reach[b0]), nr1 = has1 ? min(NB, reach[b1]) : 0;
+        const int nrow0 = 16 + 16 * nr0, nrow1 = has1 ? 16 + 16 * nr1 : 0;
+        // ---- 1. panel 0 from the hand-over or the prefetched HBM rows
+        cplx<T> a[16];
+        {
+            const bool from_nx = rrel < nx0;
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const bool on = ent_on(p0, c, nrow0);
+                const cplx<T> x = NX0[(from_nx ? rrel : 0) * PS + c];
+                a[c].re = on ? (from_nx ? x.re : pf[c].re) : T(0);
+                a[c].im = on ? (from_nx ? x.im : pf[c].im) : T(0);
+            }
+        }
+        // panel 1's rows not handed over: from HBM now (untouched so far)
+        if (has1) prefetch(p1, nrow1, nx1);
+        int bad = factor_row(a, nb0);
+        panel_out(a, p0, nb0, nrow0, PL0, PD0);
+        // the prefetched rows of panel 1's column join the hand-over
+        if (has1 && own && rrel >= nx1 && rrel < nrow1) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) NX1[rrel * PS + c] = pf[c];
+        }
+        __syncthreads();
+        // ---- 2. panel 0's update of panel 1's column: tiles (ti, 0) right
+        // below panel 0's diagonal block, ti < nr0, in NX1
+        if (has1) {
+            for (int ti = wave; ti < nr0; ti += 8) {
+                V4 ur = zero4<T>(), ui = zero4<T>();
+                tile_sum(ur, ui, PL0, PD0, 0, 16 * ti);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = 16 * ti + li, cc = mfma_row<T>(lk, j);     // relative to p1
+                    const int d = r - cc;
+                    if (d >= 0 && d <= bp && p1 + r < Mx && p1 + cc < Mx) {
+                        const cplx<T> c0 = NX1[r * PS + cc];
+                        NX1s[r * PS + cc] = V2{c0.re - ur[j], c0.im - ui[j]};
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // ---- 3. panel 1 from NX1, factored; the next panel 0's rows that
+        // this pass does not update: from HBM now
+        const int nt = has1 ? max(nr0 - 1, nr1) : 0;      // row blocks of the trailing update
+        if (has1) {
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const bool on = ent_on(p1, c, nrow1);
+                const cplx<T> x = NX1[(on ? rrel : 0) * PS + c];
+                a[c].re = on ? x.re : T(0);
+                a[c].im = on ? x.im : T(0);
+            }
+        }
+        if (b0 + 2 < nblk) prefetch(p0 + 32, 16 + 16 * min(NB, reach[b0 + 2]), 16 * nt);
+        if (has1) {
+            bad |= factor_row(a, nb1);
+            panel_out(a, p1, nb1, nrow1, PL1, PD1);
+        }
+        if (tid == 0 && bad != 0) atomicOr(flag, 1);
+        __syncthreads();
+        // ---- 4. trailing tiles (ti, tj), tj <= ti < nt, of the rows and
+        // columns from q1 = p1 + 16 on, dealt round-robin to the waves
+        const int q1 = p1 + 16;
+        const int ntile = nt * (nt + 1) / 2;
+        auto c_on = [&](int ti, int tj, int j) {
+            const int r = q1 + 16 * ti + li, cc = q1 + 16 * tj + mfma_row<T>(lk, j);
+            const int d = r - cc;
+            return d >= 0 && d <= bp && r < Mx && cc < Mx;
+        };
+        auto c_load = [&](int t, cplx<T> (&cv)[4]) {
+            int ti, tj;
+            tile_ij(min(t, ntile - 1), ti, tj);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int r = q1 + 16 * ti + li, cc = q1 + 16 * tj + mfma_row<T>(lk, j);
+                const int off = c_on(ti, tj, j) ? cc * bp1 + (r - cc) : 0;
+                const cplx<T>* e = base + off;
+                cv[j].re = e->re;
+                cv[j].im = e->im;
+            }
+        };
+        auto c_update = [&](int t, const cplx<T> (&cv)[4]) {
+            int ti, tj;
+            tile_ij(t, ti, tj);
+            V4 ur = zero4<T>(), ui = zero4<T>();
+            tile_sum(ur, ui, PL0, PD0, 16 + 16 * tj, 16 + 16 * ti);
+            tile_sum(ur, ui, PL1, PD1, 16 * tj, 16 * ti);
+            if (tj == 0) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c_on(ti, tj, j))
+                        NX0s[(16 * ti + li) * PS + mfma_row<T>(lk, j)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+            } else if (tj == 1) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (c_on(ti, tj, j))
+                        NX1s[(16 * (ti - 1) + li) * PS + mfma_row<T>(lk, j)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = q1 + 16 * ti + li, cc = q1 + 16 * tj + mfma_row<T>(lk, j);
+                    if (c_on(ti, tj, j)) gbase[cc * bp1 + (r - cc)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+                }
+            }
+        };
+        {
+            constexpr int NBUF = 4;
+            cplx<T> cb[NBUF][4];
+            int t = wave;
+#pragma unroll
+            for (int i = 0; i + 1 < NBUF; ++i) c_load(t + 8 * i, cb[i]);
+            while (t < ntile) {
+#pragma unroll
+                for (int i = 0; i < NBUF; ++i) {
+                    c_load(t + 8 * (NBUF - 1), cb[(i + NBUF - 1) % NBUF]);
+                    if (t < ntile) c_update(t, cb[i]);
+                    t += 8;
+                }
+            }
+        }
+        nx0 = 16 * nt;
+        nx1 = max(0, 16 * (nt - 1));
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(512) band_ldl_panel2_kernel(cplx<T>* __restrict__ LB, int Mx, int bp, int ncplx,
+                                                             int nsys, const int* __restrict__ reach,
+                                                             int* __restrict__ flag) {
+    extern __shared__ unsigned char smem_raw[];
+    const size_t stride = (size_t)Mx * (bp + 1);
+    const int b = blockIdx.x;
+    if (b < ncplx) {
+        panel2_factor_system<T, false>(LB + (size_t)b * stride, Mx, bp, reach, flag, smem_raw);
+        return;
+    }
+    const int s0 = ncplx + 2 * (b - ncplx);
+    panel2_factor_system<T, true>(LB + (size_t)s0 * stride, Mx, bp, reach, flag, smem_raw);
+    if (s0 + 1 < nsys) {
+        __syncthreads();
+        panel2_factor_system<T, true>(LB + (size_t)(s0 + 1) * stride, Mx, bp, reach, flag, smem_raw);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -938,8 +1241,11 @@ static size_t stream_smem(int bp, size_t es) { return 2 * 16 * (size_t)(bp + 1) 
 template <typename T>
 static size_t panel_smem() { return (2 * 256 * (size_t)PS + 16) * sizeof(cplx<T>); }
 
+
+
 template <typename T>
 size_t band_ldl_smem(int bp) {
+    // (the two-panel kernel, FP32 only, needs more: its launch requests it)
     return use_window<T>(bp) ? window_smem<T>(bp) : std::max(stream_smem(bp, sizeof(T)), panel_smem<T>());
 }
 
@@ -950,6 +1256,22 @@ hipError_t launch_band_ldl(void* LB, int Mx, int bp, int nsys, int nreal, const 
     // the panel kernel takes the trailing real systems in pairs
     const int ncplx = nsys - nreal;
     const int nwg = ncplx + (nreal + 1) / 2;
+    if constexpr (sizeof(T) == 4) {
+        // FP32: the two-panel kernel is also the automatic choice where the
+        // one-panel kernel would be
+        if (kernel == FACTOR_PANEL2 || (kernel == FACTOR_AUTO && !use_window<T>(bp) && bp != 128)) {
+            if (bp > 256 || bp % 16 != 0 || (size_t)Mx * (bp + 1) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+            const size_t smem = panel2_smem<T>();
+            hipError_t e = hipFuncSetAttribute((const void*)band_ldl_panel2_kernel<T>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(band_ldl_panel2_kernel<T>, dim3(nwg), dim3(512), smem, st, static_cast<cplx<T>*>(LB),
+                               Mx, bp, ncplx, nsys, reach, flag);
+            return hipGetLastError();
+        }
+    } else {
+        if (kernel == FACTOR_PANEL2) return hipErrorInvalidValue;   // its LDS does not fit in FP64
+    }
     if (kernel == FACTOR_PANEL || (kernel == FACTOR_AUTO && !use_window<T>(bp) && !(sizeof(T) == 4 && bp == 128))) {
         if (bp > 256 || bp % 16 != 0 || (size_t)Mx * (bp + 1) >= ((size_t)1 << 31)) return hipErrorInvalidValue;
         const size_t smem = panel_smem<T>();

@@ -725,7 +725,8 @@ extern "C" int stfd_get_tuning(const stfd_problem* p, stfd_tuning* t) {
 extern "C" int stfd_set_tuning(stfd_problem* p, const stfd_tuning* t) {
     auto tile_ok = [](int m) { return m == 64 || m == 128; };
     if (!p || !t || t->sweep_tile_min_rhs < 0 || !tile_ok(t->gemm_tile_m_fp32) || !tile_ok(t->gemm_tile_m_fp64) ||
-        (t->gemm_n_fast != 0 && t->gemm_n_fast != 1) || t->factor_kernel < 0 || t->factor_kernel > 2 ||
+        (t->gemm_n_fast != 0 && t->gemm_n_fast != 1) || t->factor_kernel < 0 || t->factor_kernel > 3 ||
+        (t->factor_kernel == 3 && !is_fp32(p)) ||
         (t->factor_pack_real != 0 && t->factor_pack_real != 1) ||
         (t->sweep_pack_real != 0 && t->sweep_pack_real != 1) ||
         (t->gemm_tile_n_fp64 != 64 && !(t->gemm_tile_n_fp64 == 128 && t->gemm_tile_m_fp64 == 128)))

@@ -8,7 +8,8 @@ through the same sweeps.
 
 Cases: padded half-bandwidths 16 to 256 on thin rectangles (ragged last
 blocks), the L-shape (the envelope narrows to half the band in its lower
-rows) and a square; both precisions.  Bound as for the sweeps: the banded
+rows) and a square; both precisions; in FP32 also the two-panel kernel
+(two 16-column panels per pass, an odd or even number of blocks).  Bound as for the sweeps: the banded
 factorization without pivoting has a backward error of order (b + 1) u
 |L||D||L^T| (Higham, Thm. 9.3), so the relative forward error of the solve
 stays within 4 (b + 1) u kappa_2(S_k) (the lane-chain sweeps are used, so
@@ -55,7 +56,7 @@ def test_factor_kernels_match_oracle(precision, name, mesh):
     rng = np.random.default_rng(8700)
     G = rng.standard_normal((2, 2 * n_sys, Mx.shape[0]))
     out = {}
-    for kernel in (2, 1):
+    for kernel in ((3, 2, 1) if precision == "fp32" else (2, 1)):
         prob, Gh, Z = _solve(mesh, At, Mt, precision, kernel, G)
         lam = prob.system_lambdas()
         b = prob.setup_report["half_band"]
@@ -76,9 +77,9 @@ def test_factor_kernels_match_oracle(precision, name, mesh):
               flush=True)
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_panel_factor_full_solve_matches_oracle(precision):
-    """A refined solve on the L-shape with the panel kernel: error and
+@pytest.mark.parametrize("precision,kernel", [("fp64", 2), ("fp32", 2), ("fp32", 3)])
+def test_panel_factor_full_solve_matches_oracle(precision, kernel):
+    """A refined solve on the L-shape with the panel kernels: error and
     residual against the oracle's direct solve of K_h <= 1e-10."""
     mesh, t = w.lshape_mesh(16), w.paper_times(2)
     At, Mt, Ct = tm.kernel(t)
@@ -86,7 +87,7 @@ def test_panel_factor_full_solve_matches_oracle(precision):
     from oracle import load
     Fo = load.assemble_load(M10, load.modes_cell_means(mesh, t, w.random_modes(8710)), Ct)
     prob = stfd.Problem(stfd.Space(mesh), At, Mt, precision=precision, rtol=1e-11, tuning=None)
-    prob.set_tuning(factor_kernel=2)
+    prob.set_tuning(factor_kernel=kernel)
     prob.factor()
     F = torch.from_numpy(np.ascontiguousarray(Fo.T[None])).to("cuda:0")
     U = torch.empty_like(F)
@@ -99,8 +100,7 @@ def test_panel_factor_full_solve_matches_oracle(precision):
     assert so.rel_residual(At, Mt, Mx, Ax, Fo, Uh) <= 1e-10
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("kernel", [1, 2])
+@pytest.mark.parametrize("precision,kernel", [("fp64", 1), ("fp64", 2), ("fp32", 1), ("fp32", 2), ("fp32", 3)])
 @pytest.mark.parametrize("nt", [8, 7, 12])
 def test_real_systems_packed_match_complex_form(precision, kernel, nt):
     """The real systems of Alg. FD (real lambda, ordered last) factored two
