@@ -929,10 +929,11 @@ __global__ void __launch_bounds__(512) band_ldl_panel_kernel(cplx<T>* __restrict
 //     takes panel 0's update there (tiles on the matrix cores);
 //  3. panel 1 is factored in registers from NX1, written out, PL1 and PD1 to
 //     LDS;
-//  4. the trailing tiles right of block b1 take both panels' update, summed
-//     on their own and subtracted once: C -= L0 D0 L0^T + L1 D1 L1^T; the
-//     tiles of blocks b0 + 2 and b0 + 3 (the next pass's panels) go to NX0
-//     and NX1 instead of HBM.
+//  4. the trailing tiles right of block b1 take both panels' update, each
+//     summed on its own: C - L0 D0 L0^T - L1 D1 L1^T, the roundings of two
+//     passes of the one-panel kernel (whose factor this one reproduces bit
+//     for bit); the tiles of blocks b0 + 2 and b0 + 3 (the next pass's
+//     panels) go to NX0 and NX1 instead of HBM.
 // LDS (complex, stride PS): PL0 [272], PL1 [256], NX0 [256], NX1 [272] rows,
 // PD0 and PD1: 138.4 KB in FP32.
 // ---------------------------------------------------------------------------
@@ -1155,27 +1156,31 @@ __device__ __forceinline__ void panel2_factor_system(cplx<T>* __restrict__ base,
                 cv[j].im = e->im;
             }
         };
+        // each panel's update summed on its own and subtracted in panel
+        // order, C - u0 - u1: the roundings of the one-panel kernel, whose
+        // factor this one reproduces bit for bit
         auto c_update = [&](int t, const cplx<T> (&cv)[4]) {
             int ti, tj;
             tile_ij(t, ti, tj);
-            V4 ur = zero4<T>(), ui = zero4<T>();
-            tile_sum(ur, ui, PL0, PD0, 16 + 16 * tj, 16 + 16 * ti);
-            tile_sum(ur, ui, PL1, PD1, 16 * tj, 16 * ti);
+            V4 ur0 = zero4<T>(), ui0 = zero4<T>(), ur1 = zero4<T>(), ui1 = zero4<T>();
+            tile_sum(ur0, ui0, PL0, PD0, 16 + 16 * tj, 16 + 16 * ti);
+            tile_sum(ur1, ui1, PL1, PD1, 16 * tj, 16 * ti);
+            V2 v[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) v[j] = V2{(cv[j].re - ur0[j]) - ur1[j], (cv[j].im - ui0[j]) - ui1[j]};
             if (tj == 0) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (c_on(ti, tj, j))
-                        NX0s[(16 * ti + li) * PS + mfma_row<T>(lk, j)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+                    if (c_on(ti, tj, j)) NX0s[(16 * ti + li) * PS + mfma_row<T>(lk, j)] = v[j];
             } else if (tj == 1) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    if (c_on(ti, tj, j))
-                        NX1s[(16 * (ti - 1) + li) * PS + mfma_row<T>(lk, j)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+                    if (c_on(ti, tj, j)) NX1s[(16 * (ti - 1) + li) * PS + mfma_row<T>(lk, j)] = v[j];
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int r = q1 + 16 * ti + li, cc = q1 + 16 * tj + mfma_row<T>(lk, j);
-                    if (c_on(ti, tj, j)) gbase[cc * bp1 + (r - cc)] = V2{cv[j].re - ur[j], cv[j].im - ui[j]};
+                    if (c_on(ti, tj, j)) gbase[cc * bp1 + (r - cc)] = v[j];
                 }
             }
         };

@@ -344,16 +344,25 @@ size_t gemm_resid_partials(int M, int N, int batch) {
 constexpr int SPATIAL_KC = 16;
 
 template <int NNZ>
-__global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, const int* __restrict__ rowptr,
+__global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, int nrhs, const int* __restrict__ rowptr,
                                                             const int* __restrict__ col,
                                                             const double* __restrict__ valM,
                                                             const double* __restrict__ valA,
                                                             const double* __restrict__ U, double* __restrict__ P,
                                                             const int* __restrict__ gate) {
     if (gate && *gate) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int k0 = blockIdx.y * SPATIAL_KC;
-    const int batch = blockIdx.z;
+    // workgroup w (a 1D grid of 8 per_xcd) runs on XCD w mod 8: each XCD
+    // takes a contiguous range of the (row block, time chunk, RHS) blocks,
+    // row blocks fastest, so that the neighbouring row blocks whose rows a
+    // stencil reads share its L2
+    const unsigned gx = (Mx + 255) / 256, gy = (Nt + SPATIAL_KC - 1) / SPATIAL_KC;
+    const unsigned total = gx * gy * (unsigned)nrhs;
+    const unsigned per_xcd = gridDim.x / 8;
+    const unsigned logical = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (logical >= total) return;
+    const int i = (int)(logical % gx) * blockDim.x + threadIdx.x;
+    const int k0 = (int)((logical / gx) % gy) * SPATIAL_KC;
+    const int batch = (int)(logical / (gx * gy));
     if (i >= Mx) return;
     const int e0 = rowptr[i], n = rowptr[i + 1] - e0;
     int c[NNZ];
@@ -389,9 +398,11 @@ __global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, cons
 
 hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, const int* col, const double* valM,
                                 const double* valA, const double* U, double* P, hipStream_t st) {
-    dim3 grid((Mx + 255) / 256, (Nt + SPATIAL_KC - 1) / SPATIAL_KC, nrhs);
-    hipLaunchKernelGGL(spatial_apply_kernel<8>, grid, dim3(256), 0, st, Mx, Nt, rowptr, col, valM, valA, U, P,
-                       launch_gate());
+    // (8 per_xcd workgroups: those past the blocks return)
+    const unsigned gx = (Mx + 255) / 256, gy = (Nt + SPATIAL_KC - 1) / SPATIAL_KC;
+    const unsigned total = gx * gy * (unsigned)nrhs;
+    hipLaunchKernelGGL(spatial_apply_kernel<8>, dim3(8 * ((total + 7) / 8)), dim3(256), 0, st, Mx, Nt, nrhs, rowptr,
+                       col, valM, valA, U, P, launch_gate());
     return hipGetLastError();
 }
 

@@ -9,7 +9,8 @@ through the same sweeps.
 Cases: padded half-bandwidths 16 to 256 on thin rectangles (ragged last
 blocks), the L-shape (the envelope narrows to half the band in its lower
 rows) and a square; both precisions; in FP32 also the two-panel kernel
-(two 16-column panels per pass, an odd or even number of blocks).  Bound as for the sweeps: the banded
+(two 16-column panels per pass, an odd or even number of blocks), whose
+solves must equal the one-panel kernel's bit for bit.  Bound as for the sweeps: the banded
 factorization without pivoting has a backward error of order (b + 1) u
 |L||D||L^T| (Higham, Thm. 9.3), so the relative forward error of the solve
 stays within 4 (b + 1) u kappa_2(S_k) (the lane-chain sweeps are used, so
@@ -75,6 +76,11 @@ def test_factor_kernels_match_oracle(precision, name, mesh):
         out[kernel] = (Z, worst)
         print(f"  {name} {precision} kernel {kernel}: M_x {Mx.shape[0]}, b {b}, worst error / bound {worst:.2e}",
               flush=True)
+    if precision == "fp32":
+        # the two-panel kernel subtracts each panel's update on its own, in
+        # panel order: the one-panel kernel's roundings, so its factor and
+        # every solve through it are the same bit for bit
+        assert np.array_equal(out[3][0], out[2][0])
 
 
 @pytest.mark.parametrize("precision,kernel", [("fp64", 2), ("fp32", 2), ("fp32", 3)])
