@@ -87,11 +87,18 @@ typedef struct {
     double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
     int max_refine;       /* maximum number of refinement corrections (default 30) */
     int method;           /* STFD_METHOD_FD (default) or STFD_METHOD_BSC */
-    int inner_refine;     /* FD only, 0 or 1: steps of refinement of the spatial
-                             solves inside each application (the residual
-                             g_k - (M_x + lambda_k A_x) z_k formed in FP64 from
-                             the stored g_k and z_k, solved with the same band
-                             factors, the correction added to z_k).  Default 0. */
+    int inner_refine;     /* FD only, 0 to 3: steps of refinement of the spatial
+                             solves inside each application.  With k > 0, G is
+                             kept in FP64, solved once by the band factors and
+                             then k times on its residual g_k - (M_x + lambda_k
+                             A_x) z_k (formed in FP64), the solutions summed in
+                             FP64 for an FP64 back transform: in the FP32 form
+                             neither G's nor Z's FP32 rounding reaches U, only
+                             the factors' error, which each step contracts.  The
+                             FP32 form then needs fp64_transforms bits 0 and 2
+                             (STFD_EINVAL otherwise).  Costs one pair of sweeps
+                             per step and 2 x 8 M_x x 2 n_sys bytes per
+                             right-hand side of device memory.  Default 0. */
     int graph;            /* FD only: 1 = the refinement rounds of stfd_fd_solve and
                              stfd_batch_solve run as captured HIP graphs
                              (apply, residual and a device-side convergence check;

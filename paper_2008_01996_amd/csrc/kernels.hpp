@@ -66,13 +66,15 @@ size_t gemm_resid_partials(int M, int N, int batch);
 
 hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, const int* col, const double* valM,
                                 const double* valA, const double* U, double* P, hipStream_t st);
-// G -= (M_x + lambda_k A_x) Z for every system and right-hand side (FP64 arithmetic on working-precision data)
-template <typename T>
+// R = G - (M_x + lambda_k A_x) Z for every system and right-hand side (FP64
+// G and Z, FP64 arithmetic, R in TR)
+template <typename TR>
 hipError_t launch_spatial_resid(int Mx, int nsys, int nrhs, const int* rowptr, const int* col, const double* valM,
-                                const double* valA, const double* lam, void* G, const void* Z, hipStream_t st);
-// y += x, n elements
-template <typename T>
-hipError_t launch_add(void* y, const void* x, size_t n, hipStream_t st);
+                                const double* valA, const double* lam, const double* G, const double* Z, void* R,
+                                hipStream_t st);
+// y = x (ACC false) or y += x (ACC true), n elements, x converted to TY
+template <typename TY, typename TX, bool ACC>
+hipError_t launch_convert(void* y, const void* x, size_t n, hipStream_t st);
 hipError_t launch_reduce_partials(const double* partial, size_t blocks, int nrhs, double* norms, hipStream_t st);
 hipError_t launch_fill_zero(double* p, size_t n, hipStream_t st);
 

@@ -406,74 +406,87 @@ hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, con
     return hipGetLastError();
 }
 
-// Residual of the spatial systems of step 3 of Algorithm FD, for one step of
-// refinement inside an application: R = G - (M_x + lambda_k A_x) Z for every
-// system k and right-hand side, with the CSR products and the subtraction in
-// FP64 from the stored (working-precision) G and Z; R overwrites G.  Layout of
-// G, Z per RHS: column-major M_x x 2 n_sys, real parts of system k in column
-// k, imaginary parts in column n_sys + k.  One thread per row; grid.y runs
-// over the systems, grid.z over the right-hand sides.
-template <typename T>
+// Residual of the spatial systems of step 3 of Algorithm FD, for the
+// refinement of the spatial solves inside an application: R = G - (M_x +
+// lambda_k A_x) Z for every system k and right-hand side, the CSR products and
+// the subtraction in FP64 from FP64 G and Z, R rounded to the working
+// precision (the band factors solve it).  Layout of G, Z, R per RHS:
+// column-major M_x x 2 n_sys, real parts of system k in column k, imaginary
+// parts in column n_sys + k.  One thread per row; grid.y runs over the
+// systems, grid.z over the right-hand sides.
+template <typename TR>
 __global__ void __launch_bounds__(256) spatial_resid_kernel(int Mx, int nsys, const int* __restrict__ rowptr,
                                                             const int* __restrict__ col,
                                                             const double* __restrict__ valM,
                                                             const double* __restrict__ valA,
-                                                            const double* __restrict__ lam, T* __restrict__ G,
-                                                            const T* __restrict__ Z, const int* __restrict__ gate) {
+                                                            const double* __restrict__ lam,
+                                                            const double* __restrict__ G,
+                                                            const double* __restrict__ Z, TR* __restrict__ R,
+                                                            const int* __restrict__ gate) {
     if (gate && *gate) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Mx) return;
     const int k = blockIdx.y;
     const size_t rhs = (size_t)blockIdx.z * 2 * nsys * Mx;
-    const T* zr = Z + rhs + (size_t)k * Mx;
-    const T* zi = Z + rhs + (size_t)(nsys + k) * Mx;
-    T* gr = G + rhs + (size_t)k * Mx;
-    T* gi = G + rhs + (size_t)(nsys + k) * Mx;
+    const size_t cr = rhs + (size_t)k * Mx, ci = rhs + (size_t)(nsys + k) * Mx;
     const double lr = lam[2 * k], li = lam[2 * k + 1];
     double sr = 0.0, si = 0.0;
     for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
         const int j = col[e];
         const double mr = valM[e] + lr * valA[e], mi = li * valA[e];
-        const double xr = static_cast<double>(zr[j]), xi = static_cast<double>(zi[j]);
+        const double xr = Z[cr + j], xi = Z[ci + j];
         sr += mr * xr - mi * xi;
         si += mr * xi + mi * xr;
     }
-    gr[i] = static_cast<T>(static_cast<double>(gr[i]) - sr);
-    gi[i] = static_cast<T>(static_cast<double>(gi[i]) - si);
+    R[cr + i] = static_cast<TR>(G[cr + i] - sr);
+    R[ci + i] = static_cast<TR>(G[ci + i] - si);
 }
 
-template <typename T>
+template <typename TR>
 hipError_t launch_spatial_resid(int Mx, int nsys, int nrhs, const int* rowptr, const int* col, const double* valM,
-                                const double* valA, const double* lam, void* G, const void* Z, hipStream_t st) {
+                                const double* valA, const double* lam, const double* G, const double* Z, void* R,
+                                hipStream_t st) {
     dim3 grid((Mx + 255) / 256, nsys, nrhs);
-    hipLaunchKernelGGL(spatial_resid_kernel<T>, grid, dim3(256), 0, st, Mx, nsys, rowptr, col, valM, valA, lam,
-                       static_cast<T*>(G), static_cast<const T*>(Z), launch_gate());
+    hipLaunchKernelGGL(spatial_resid_kernel<TR>, grid, dim3(256), 0, st, Mx, nsys, rowptr, col, valM, valA, lam, G,
+                       Z, static_cast<TR*>(R), launch_gate());
     return hipGetLastError();
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) add_kernel(T* __restrict__ y, const T* __restrict__ x, size_t n,
-                                                  const int* __restrict__ gate) {
+// y = x (ACC = false) or y += x (ACC = true), elementwise, x converted to the
+// type of y; four elements per thread and step (n need not be a multiple)
+template <typename TY, typename TX, bool ACC>
+__global__ void __launch_bounds__(256) convert_kernel(TY* __restrict__ y, const TX* __restrict__ x, size_t n,
+                                                      const int* __restrict__ gate) {
     if (gate && *gate) return;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        y[i] += x[i];
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += 4 * stride) {
+        TX v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = i + u * stride < n ? x[i + u * stride] : TX(0);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (i + u * stride < n) y[i + u * stride] = ACC ? y[i + u * stride] + static_cast<TY>(v[u]) : static_cast<TY>(v[u]);
+    }
 }
 
-template <typename T>
-hipError_t launch_add(void* y, const void* x, size_t n, hipStream_t st) {
+template <typename TY, typename TX, bool ACC>
+hipError_t launch_convert(void* y, const void* x, size_t n, hipStream_t st) {
     if (n == 0) return hipSuccess;
-    const size_t blocks = std::min<size_t>((n + 255) / 256, 16384);
-    hipLaunchKernelGGL(add_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, static_cast<T*>(y),
-                       static_cast<const T*>(x), n, launch_gate());
+    const size_t blocks = std::min<size_t>((n + 1023) / 1024, 32768);
+    hipLaunchKernelGGL((convert_kernel<TY, TX, ACC>), dim3((unsigned)blocks), dim3(256), 0, st, static_cast<TY*>(y),
+                       static_cast<const TX*>(x), n, launch_gate());
     return hipGetLastError();
 }
 
 template hipError_t launch_spatial_resid<float>(int, int, int, const int*, const int*, const double*, const double*,
-                                                const double*, void*, const void*, hipStream_t);
+                                                const double*, const double*, const double*, void*, hipStream_t);
 template hipError_t launch_spatial_resid<double>(int, int, int, const int*, const int*, const double*,
-                                                 const double*, const double*, void*, const void*, hipStream_t);
-template hipError_t launch_add<float>(void*, const void*, size_t, hipStream_t);
-template hipError_t launch_add<double>(void*, const void*, size_t, hipStream_t);
+                                                 const double*, const double*, const double*, const double*, void*,
+                                                 hipStream_t);
+template hipError_t launch_convert<float, double, false>(void*, const void*, size_t, hipStream_t);
+template hipError_t launch_convert<double, float, false>(void*, const void*, size_t, hipStream_t);
+template hipError_t launch_convert<double, float, true>(void*, const void*, size_t, hipStream_t);
+template hipError_t launch_convert<double, double, true>(void*, const void*, size_t, hipStream_t);
 
 // Bartels-Stewart with the complex Schur form (Alg. BSc, Sec. 4.3), step 3:
 // once z_k is solved, the right-hand sides of the systems still to come take

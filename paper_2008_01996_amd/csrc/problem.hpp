@@ -48,7 +48,8 @@ struct stfd_problem {
     int nrhs_cap = 0;
     void* d_T1 = nullptr;       // Mx x 2Nt per RHS (FP32 or FP64)
     void* d_G = nullptr;        // Mx x 2nsys per RHS
-    void* d_Gs = nullptr;       // Mx x 2nsys per RHS: G kept for the inner refinement, then its residual
+    double* d_Gs = nullptr;     // Mx x 2nsys per RHS, FP64: G kept for the inner refinement
+    double* d_Z64 = nullptr;    // Mx x 2nsys per RHS, FP64: the spatial solutions summed over the inner refinement
     double* d_P = nullptr;      // Mx x 2Nt per RHS
     double* d_R = nullptr;      // Mx x Nt per RHS
     double* d_part = nullptr;

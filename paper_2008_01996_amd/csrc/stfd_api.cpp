@@ -51,11 +51,13 @@ void free_work(stfd_problem* p) {
     (void)hipFree(p->d_T1);
     (void)hipFree(p->d_G);
     (void)hipFree(p->d_Gs);
+    (void)hipFree(p->d_Z64);
     (void)hipFree(p->d_P);
     (void)hipFree(p->d_R);
     (void)hipFree(p->d_part);
     (void)hipFree(p->d_norms);
-    p->d_T1 = p->d_G = p->d_Gs = nullptr;
+    p->d_T1 = p->d_G = nullptr;
+    p->d_Gs = p->d_Z64 = nullptr;
     p->d_P = p->d_R = p->d_part = p->d_norms = nullptr;
     p->nrhs_cap = 0;
 }
@@ -248,7 +250,8 @@ int ensure_work(stfd_problem* p, int nrhs) {
     struct { void** ptr; size_t bytes; } req[] = {
         {&p->d_T1, p->fwd_merged ? 0 : Mx * 2 * Nt * es * nrhs},
         {&p->d_G, Mx * 2 * ns * es * nrhs},
-        {&p->d_Gs, p->opts.inner_refine > 0 ? Mx * 2 * ns * es * nrhs : 0},
+        {reinterpret_cast<void**>(&p->d_Gs), p->opts.inner_refine > 0 ? Mx * 2 * ns * 8 * nrhs : 0},
+        {reinterpret_cast<void**>(&p->d_Z64), p->opts.inner_refine > 0 ? Mx * 2 * ns * 8 * nrhs : 0},
         {reinterpret_cast<void**>(&p->d_P), Mx * 2 * Nt * 8 * nrhs},
         {reinterpret_cast<void**>(&p->d_R), Mx * Nt * 8 * nrhs},
         {reinterpret_cast<void**>(&p->d_part), parts * 2 * 8},
@@ -532,7 +535,7 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     if (opts) o = *opts;
     if ((o.precision != STFD_PREC_FP32 && o.precision != STFD_PREC_FP64) || !(o.rtol >= 0.0) || o.max_refine < 0 ||
         o.max_refine >= STFD_MAX_HIST || o.fp64_transforms < 0 || o.fp64_transforms > 7 ||
-        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC) || o.inner_refine < 0 || o.inner_refine > 1 ||
+        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC) || o.inner_refine < 0 || o.inner_refine > 3 ||
         o.graph < 0 || o.graph > 1 || o.nrhs_max < 0)
         return fail(STFD_EINVAL, "fd_setup: bad options");
     {
@@ -544,6 +547,9 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     }
     if (o.method == STFD_METHOD_BSC && o.inner_refine != 0)
         return fail(STFD_EINVAL, "fd_setup: the inner refinement belongs to Algorithm FD");
+    if (o.precision == STFD_PREC_FP32 && o.inner_refine != 0 && (o.fp64_transforms & 5) != 5)
+        return fail(STFD_EINVAL, "fd_setup: the inner refinement keeps G and Z in FP64, so the FP32 form needs the "
+                                 "FP64 forward and back transforms (fp64_transforms bits 0 and 2)");
     if (o.method == STFD_METHOD_BSC) return bs_setup(space, Nt, At, Mt, o, static_cast<hipStream_t>(hip_stream), out);
     const auto t0 = std::chrono::steady_clock::now();
     Decomp D;
@@ -853,7 +859,7 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     stfd::GemmArgs g{};
     if (p->fwd_merged) {
         // step 2: G = X (W1 W2)   (Mx x 2nsys), FP64 products, G stored in
-        // the working precision
+        // the working precision (in FP64 for the inner refinement)
         g.A = X; g.B = p->d_Wfwd; g.C = inner ? p->d_Gs : p->d_G;
         g.M = Mx; g.N = 2 * ns; g.K = Nt;
         g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
@@ -861,7 +867,7 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
         g.batch = nrhs;
         {
             StageTimer tm(p, STFD_ST_FWD1, st);
-            HIPCHK(launch_gemm_tuned(p, f32 ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
+            HIPCHK(launch_gemm_tuned(p, f32 && !inner ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
                    "forward transform");
         }
         return fd_apply_rest(p, nrhs, U, st);
@@ -882,7 +888,7 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     // step 2b: G = T1 W2   (Mx x 2nsys)
     g = stfd::GemmArgs{};
     g.A = p->d_T1; g.B = (f32 && (mask & 2)) ? static_cast<const void*>(p->d_W2d) : p->d_W2;
-    g.C = inner ? p->d_Gs : p->d_G;
+    g.C = p->d_G;       // (the setup rejects the inner refinement without the merged forward)
     g.M = Mx; g.N = 2 * ns; g.K = 2 * Nt;
     g.lda = Mx; g.ldb = 2 * ns; g.ldc = Mx;
     g.strideA = (long long)Mx * 2 * Nt; g.strideC = (long long)Mx * 2 * ns;
@@ -897,38 +903,71 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
     return fd_apply_rest(p, nrhs, U, st);
 }
 
-// steps 3 and 4 of an FD application, from G (or Gs with the inner
-// refinement) to U += Re(Z Xb)
+// steps 3 and 4 of an FD application with the refinement of the spatial
+// solves: G (FP64, in Gs) is solved once by the band factors, the solution
+// kept in FP64 (Z64); then, opts.inner_refine times, R = G - (M_x + lambda_k
+// A_x) Z64 in FP64, solved by the same factors and added to Z64; finally
+// U += Re(Z64 Xb) in FP64.  In the FP32 form G is rounded to FP32 for the
+// factors and every solution widened back, so neither G's nor Z's FP32
+// rounding stays in the result: only the factors' error, which each step
+// contracts.
+int fd_apply_inner(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
+    const bool f32 = is_fp32(p);
+    const int Mx = p->Mx, ns = p->nsys;
+    const size_t n = (size_t)Mx * 2 * ns * nrhs;
+    int rc;
+    if (f32) {
+        {
+            StageTimer tm(p, STFD_ST_INNER, st);
+            HIPCHK((stfd::launch_convert<float, double, false>(p->d_G, p->d_Gs, n, st)), "inner: G to FP32");
+        }
+        rc = spatial_sweeps(p, nrhs, p->d_G, p->d_G, st, true);
+        if (rc) return rc;
+        StageTimer tm(p, STFD_ST_INNER, st);
+        HIPCHK((stfd::launch_convert<double, float, false>(p->d_Z64, p->d_G, n, st)), "inner: Z to FP64");
+    } else {
+        rc = spatial_sweeps(p, nrhs, p->d_Gs, p->d_Z64, st, true);
+        if (rc) return rc;
+    }
+    for (int s = 0; s < p->opts.inner_refine; ++s) {
+        {
+            StageTimer tm(p, STFD_ST_INNER, st);
+            HIPCHK(f32 ? stfd::launch_spatial_resid<float>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA,
+                                                           p->d_lam, p->d_Gs, p->d_Z64, p->d_G, st)
+                       : stfd::launch_spatial_resid<double>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM,
+                                                            p->d_valA, p->d_lam, p->d_Gs, p->d_Z64, p->d_G, st),
+                   "inner residual");
+        }
+        rc = spatial_sweeps(p, nrhs, p->d_G, p->d_G, st, true);
+        if (rc) return rc;
+        StageTimer tm(p, STFD_ST_INNER, st);
+        HIPCHK((f32 ? stfd::launch_convert<double, float, true>(p->d_Z64, p->d_G, n, st)
+                    : stfd::launch_convert<double, double, true>(p->d_Z64, p->d_G, n, st)),
+               "inner update");
+    }
+    // step 4: U += Re(Z64 Xb), FP64
+    stfd::GemmArgs g{};
+    g.A = p->d_Z64; g.B = f32 ? static_cast<const void*>(p->d_Xbd) : p->d_Xb; g.C = U;
+    g.M = Mx; g.N = p->Nt; g.K = 2 * ns;
+    g.lda = Mx; g.ldb = p->Nt; g.ldc = Mx;
+    g.strideA = (long long)Mx * 2 * ns; g.strideC = (long long)Mx * p->Nt;
+    g.batch = nrhs; g.alpha = 1.0;
+    StageTimer tm(p, STFD_ST_BACK, st);
+    HIPCHK(launch_gemm_tuned(p, stfd::GEMM_D_D_ADD_D, g, st), "back transform");
+    return STFD_OK;
+}
+
+// steps 3 and 4 of an FD application, from G to U += Re(Z Xb)
 int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
     const bool f32 = is_fp32(p);
     const int Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
     const bool inner = p->opts.inner_refine > 0;
     const int mask = f32 ? p->opts.fp64_transforms : 7;
     stfd::GemmArgs g{};
-    // step 3: spatial solves, in place in G (with the inner refinement: G
-    // kept in Gs, Z into G; then Gs -= S_k Z in FP64, solved in place, and
-    // the correction added to Z)
-    int rc = spatial_sweeps(p, nrhs, inner ? p->d_Gs : p->d_G, p->d_G, st, true);
+    if (inner) return fd_apply_inner(p, nrhs, U, st);
+    // step 3: spatial solves, in place in G
+    int rc = spatial_sweeps(p, nrhs, p->d_G, p->d_G, st, true);
     if (rc) return rc;
-    if (inner) {
-        {
-            StageTimer tm(p, STFD_ST_INNER, st);
-            HIPCHK(f32 ? stfd::launch_spatial_resid<float>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA,
-                                                           p->d_lam, p->d_Gs, p->d_G, st)
-                       : stfd::launch_spatial_resid<double>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM,
-                                                            p->d_valA, p->d_lam, p->d_Gs, p->d_G, st),
-                   "inner residual");
-        }
-        rc = spatial_sweeps(p, nrhs, p->d_Gs, p->d_Gs, st, true);
-        if (rc) return rc;
-        {
-            StageTimer tm(p, STFD_ST_INNER, st);
-            const size_t n = (size_t)Mx * 2 * ns * nrhs;
-            HIPCHK(f32 ? stfd::launch_add<float>(p->d_G, p->d_Gs, n, st)
-                       : stfd::launch_add<double>(p->d_G, p->d_Gs, n, st),
-                   "inner update");
-        }
-    }
     // step 4: U += Re(Z Xb)
     g = stfd::GemmArgs{};
     g.A = p->d_G; g.B = (f32 && (mask & 4)) ? static_cast<const void*>(p->d_Xbd) : p->d_Xb; g.C = U;
