@@ -133,10 +133,18 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
     const cplx<T>* libase = LI + (size_t)sys * nblk * TB * TB;
     const cplx<T>* baseB = LB + (size_t)sysB * Mx * bp1;
     const cplx<T>* libaseB = LI + (size_t)sysB * nblk * TB * TB;
-    // an operand's imaginary slot: B's real part of the same entry
-    auto im_of = [&](const cplx<T>* e, const cplx<T>* a, const cplx<T>* b) -> T {
-        if constexpr (PAIR) return b[e - a].re;
-        else return e->im;
+    // factor and inverse entries by index from a workgroup-uniform base, the
+    // byte offset in 32 bits (one system's band is below 4 GiB, checked by
+    // the launcher): the loads take the scalar-base form, with no 64-bit
+    // address arithmetic per lane.  An operand's imaginary slot is B's real
+    // part of the same entry in PAIR mode.
+    auto entry = [](const cplx<T>* b, uint32_t i) -> const cplx<T>* {
+        return reinterpret_cast<const cplx<T>*>(reinterpret_cast<const char*>(b) + i * (uint32_t)sizeof(cplx<T>));
+    };
+    auto load_op = [&](const cplx<T>* a, const cplx<T>* b, uint32_t i) -> cplx<T> {
+        const cplx<T>* e = entry(a, i);
+        if constexpr (PAIR) return cplx<T>{e->re, entry(b, i)->re};
+        else return *e;
     };
 
     // tile of the input vector for block j, accumulator layout.  The loads
@@ -169,25 +177,32 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
     };
     // operand of Q_jc for k-step kk (lane: m = n, k = 4 kk + g), raw value
     // (address clamped) and whether it lies in the band
-    // Factor operand of Q_jc for k-step kk (lane: m = n, k = 4 kk + g):
+    // Factor operand of Q_jc for k-step kk (lane: m = n, k = kof(kk)):
     // forward L[16 j + m][16 c + k], backward L[16 c + k][16 j + m].  In the
     // band storage its index is linear in the blocks,
-    //   forward  (16 c + 4 kk + g)(bp + 1) + 16 (j - c) + n - 4 kk - g
-    //          = 16 bp c + 16 j + n + (4 kk + g) bp,
-    //   backward 16 bp j + n bp + 16 c + 4 kk + g,
+    //   forward  (16 c + k)(bp + 1) + 16 (j - c) + n - k
+    //          = 16 bp c + 16 j + n + k bp,
+    //   backward 16 bp j + n bp + 16 c + k,
     // and always in range except in the last block (clamped).  Entries of
     // rows past M_x are zero in the storage; only the last tile of the band
     // (d > bp there for some lanes) and columns past M_x need masking where
     // the value is used (q_on).
+    // The order of k in the products with Q is free (the same for Q and x):
+    // forward, k = 4 kk + g puts a lane group's four k-steps in four
+    // columns, its 16 lanes reading 16 consecutive entries of each; backward,
+    // k = 4 g + kk gives every lane four consecutive entries of one column
+    // (its row of L_cj^T), so a wave's four loads of a tile touch 16 columns
+    // instead of 64 in each.
+    auto kof = [&](int kk) { return FWD ? 4 * kk + g : 4 * g + kk; };
     const int qlast = Mx * bp1 - 1;
-    auto q_index = [&](int j, int c, int kk) -> int {
-        const int i = FWD ? TB * bp * c + TB * j + n + (4 * kk + g) * bp
-                          : TB * bp * j + n * bp + TB * c + 4 * kk + g;
-        return min(max(i, 0), qlast);
+    auto q_index = [&](int j, int c, int kk) -> uint32_t {
+        const int i = FWD ? TB * bp * c + TB * j + n + kof(kk) * bp
+                          : TB * bp * j + n * bp + TB * c + kof(kk);
+        return (uint32_t)min(max(i, 0), qlast);
     };
     auto q_on = [&](int j, int c, int kk) {
-        const int d = FWD ? TB * (j - c) + n - 4 * kk - g : TB * (c - j) + 4 * kk + g - n;
-        const int col = FWD ? TB * c + 4 * kk + g : TB * j + n;
+        const int d = FWD ? TB * (j - c) + n - kof(kk) : TB * (c - j) + kof(kk) - n;
+        const int col = FWD ? TB * c + kof(kk) : TB * j + n;
         return d <= bp && col < Mx;
     };
     // whether block column c couples to block j (within the band and the
@@ -198,10 +213,10 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
     };
     // operand of the diagonal inverse for k-step kk: forward L_cc^-1[m][k],
     // backward L_cc^-1[k][m]
-    auto li_addr = [&](int c, int kk) -> size_t {
+    auto li_addr = [&](int c, int kk) -> uint32_t {
         const int cc = min(max(c, 0), nblk - 1);
         const int m = n, k = 4 * kk + g;
-        return (size_t)cc * TB * TB + (FWD ? (size_t)k * TB + m : (size_t)m * TB + k);
+        return (uint32_t)(cc * TB * TB + (FWD ? k * TB + m : m * TB + k));
     };
 
     // ---- this wave's pending tiles
@@ -226,24 +241,14 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
         for (int t = 0; t < S; ++t) {
             const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) {
-                const cplx<T>* e = base + q_index(j, c, kk);
-                qx[t][kk].re = e->re;                 // raw: masked where used
-                qx[t][kk].im = im_of(e, base, baseB);
-            }
+            for (int kk = 0; kk < 4; ++kk) qx[t][kk] = load_op(base, baseB, q_index(j, c, kk));  // raw: masked where used
         }
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const cplx<T>* e = libase + li_addr(c, kk);
-            px[kk].re = e->re;
-            px[kk].im = im_of(e, libase, libaseB);
-        }
+        for (int kk = 0; kk < 4; ++kk) px[kk] = load_op(libase, libaseB, li_addr(c, kk));
         load_tile_raw(FWD ? c + 4 * S : c - 4 * S, ex[0], ex[1]);
         if (FWD) {
             const int row = min(max(TB * c + 4 * w + g, 0), Mx - 1);
-            const cplx<T>* e = base + (size_t)row * bp1;
-            dx.re = e->re;
-            dx.im = im_of(e, base, baseB);
+            dx = load_op(base, baseB, (uint32_t)(row * bp1));
         }
     };
 #pragma unroll
@@ -320,11 +325,14 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
                 }
             }
             const int delta = FWD ? ((w - c - 1) & 3) + 1 : ((c - w - 1) & 3) + 1;
-            T br[4], bi[4];
+            // the solved block, negated once here, so that the products
+            // below take the factor operands as loaded (-= Q x as += Q (-x))
+            T br[4], bi[4], pi[4];
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                br[kk] = YR[par][4 * kk + g][n];
-                bi[kk] = YI[par][4 * kk + g][n];
+                pi[kk] = YI[par][kof(kk)][n];
+                br[kk] = -YR[par][kof(kk)][n];
+                bi[kk] = -pi[kk];
             }
 #pragma unroll
             for (int t = 0; t < S; ++t) {
@@ -344,14 +352,15 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
                         const cplx<T> a = qx[t][kk];
+                        // br + i bi = -x, pi = Im x: acc += Q (-x)
                         if constexpr (PAIR) {
-                            accR[t] = mfma16x16x4<T>(-a.re, br[kk], accR[t]);
-                            accI[t] = mfma16x16x4<T>(-a.im, bi[kk], accI[t]);
+                            accR[t] = mfma16x16x4<T>(a.re, br[kk], accR[t]);
+                            accI[t] = mfma16x16x4<T>(a.im, bi[kk], accI[t]);
                         } else {
-                            accR[t] = mfma16x16x4<T>(-a.re, br[kk], accR[t]);
-                            accR[t] = mfma16x16x4<T>(a.im, bi[kk], accR[t]);
-                            accI[t] = mfma16x16x4<T>(-a.re, bi[kk], accI[t]);
-                            accI[t] = mfma16x16x4<T>(-a.im, br[kk], accI[t]);
+                            accR[t] = mfma16x16x4<T>(a.re, br[kk], accR[t]);
+                            accR[t] = mfma16x16x4<T>(a.im, pi[kk], accR[t]);
+                            accI[t] = mfma16x16x4<T>(a.re, bi[kk], accI[t]);
+                            accI[t] = mfma16x16x4<T>(a.im, br[kk], accI[t]);
                         }
                     }
                 }
@@ -420,6 +429,10 @@ static hipError_t launch_tile(const void* LB, const void* LI, const int* reach, 
                               const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun, int nreal) {
     if (bp < TB || bp % TB != 0 || bp > TILE_BPMAX || sys0 < 0 || nrun < 1 || sys0 + nrun > nsys || nrhs < 1 ||
         nreal < 0 || nreal > nrun)
+        return hipErrorInvalidValue;
+    // byte offsets inside one system's band and block inverses are 32-bit
+    const size_t nblk = ((size_t)Mx + TB - 1) / TB;
+    if ((size_t)Mx * (bp + 1) * sizeof(cplx<T>) >= (1ull << 32) || nblk * TB * TB * sizeof(cplx<T>) >= (1ull << 32))
         return hipErrorInvalidValue;
     const int slots = (bp / TB + 3) / 4;
     switch (slots) {
