@@ -24,7 +24,8 @@
 //     enters the window (c + 4S forward, c - 4S backward) takes the last;
 //   all waves: each pending tile j takes -= Q_jc x_c, Q_jc = L_jc (forward)
 //     or L_cj^T (backward), its operands loaded from the band storage
-//     straight into registers NSET steps ahead.
+//     straight into registers NSET - 1 steps ahead (issued as the step
+//     before begins, into the register set that step has just freed).
 // Every factor entry is read once for all right-hand sides of the group.
 //
 // Layouts: band storage LB[k][c][d] = L_k[c + d, c] (d = 0: D_k), padded
@@ -187,13 +188,9 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
     // rows past M_x are zero in the storage; only the last tile of the band
     // (d > bp there for some lanes) and columns past M_x need masking where
     // the value is used (q_on).
-    // The order of k in the products with Q is free (the same for Q and x):
-    // forward, k = 4 kk + g puts a lane group's four k-steps in four
-    // columns, its 16 lanes reading 16 consecutive entries of each; backward,
-    // k = 4 g + kk gives every lane four consecutive entries of one column
-    // (its row of L_cj^T), so a wave's four loads of a tile touch 16 columns
-    // instead of 64 in each.
-    auto kof = [&](int kk) { return FWD ? 4 * kk + g : 4 * g + kk; };
+    // k of lane group g in k-step kk (backward, the four groups then read
+    // four consecutive entries of each of the wave's 16 columns)
+    auto kof = [&](int kk) { return 4 * kk + g; };
     const int qlast = Mx * bp1 - 1;
     auto q_index = [&](int j, int c, int kk) -> uint32_t {
         const int i = FWD ? TB * bp * c + TB * j + n + kof(kk) * bp
@@ -225,8 +222,9 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
 #pragma unroll
     for (int t = 0; t < S; ++t) load_tile(FWD ? j0 + 4 * t : j0 - 4 * t, accR[t], accI[t]);
 
-    // Everything step s needs from memory is loaded NSET steps ahead, by
-    // every wave alike (so the counts of outstanding loads are the same on
+    // Everything step s needs from memory is loaded NSET - 1 steps ahead, at
+    // the start of step s - NSET + 1 (so that the loads are in flight during
+    // that step's work), by every wave alike (so the counts of outstanding loads are the same on
     // every path and the waits stay exact): the factor operands of the
     // wave's pending tiles, the data the owner of block c needs (the
     // diagonal inverse, the tile entering when c retires; the other waves
@@ -252,10 +250,14 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
         }
     };
 #pragma unroll
-    for (int u = 0; u < NSET; ++u) fetch(u, qa[u], pa[u], da[u], ea[u]);
+    for (int u = 0; u + 1 < NSET; ++u) fetch(u, qa[u], pa[u], da[u], ea[u]);
 
     // one step: block c = (FWD ? s : nblk - 1 - s); steps past the end only fetch
-    auto step = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2]) {
+    auto step = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2],
+                    cplx<T> (&qn)[S][4], cplx<T> (&pn)[4], cplx<T>& dn, V4 (&en)[2]) {
+        // the set step s - 1 used takes step s + NSET - 1, issued before this
+        // step's work so that the loads are in flight during it
+        fetch(s + NSET - 1, qn, pn, dn, en);
         const int c = FWD ? s : nblk - 1 - s;
         const int par = s & 1;
         if (s < nblk) {
@@ -366,12 +368,14 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
                 }
             }
         }
-        fetch(s + NSET, qx, px, dx, ex);
     };
 
     for (int s0 = 0; s0 < nblk; s0 += NSET) {
 #pragma unroll
-        for (int u = 0; u < NSET; ++u) step(s0 + u, qa[u], pa[u], da[u], ea[u]);
+        for (int u = 0; u < NSET; ++u) {
+            const int v = (u + NSET - 1) % NSET;
+            step(s0 + u, qa[u], pa[u], da[u], ea[u], qa[v], pa[v], da[v], ea[v]);
+        }
     }
 }
 
@@ -415,7 +419,9 @@ hipError_t launch_band_diag_inverse(const void* LB, void* LI, int Mx, int bp, in
 template <typename T, bool FWD, int S>
 static hipError_t launch_tile_t(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
                                 const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun, int nreal) {
-    constexpr int NSET = sizeof(T) == 4 ? 3 : 2;     // prefetch distance in steps
+    // register sets (prefetch distance NSET - 1 steps): measured best at
+    // 3 for FP32 and 2 for FP64 (whose third set costs occupancy)
+    constexpr int NSET = sizeof(T) == 4 ? 3 : 2;
     const int ncplx = nrun - nreal;
     dim3 grid(ncplx + (nreal + 1) / 2, (nrhs + TB - 1) / TB);
     hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET>), grid, dim3(256), 0, st,
