@@ -85,6 +85,13 @@ __device__ __forceinline__ typename vec4<T>::type zero4() {
 
 // value of lane l (uniform) broadcast to the whole wave through a scalar
 // register (v_readlane), without an LDS round trip
+// x through an opaque register move: what the compiler computes from the
+// result cannot be hoisted out of the loop the move sits in
+__device__ __forceinline__ int opaque_int(int x) {
+    int r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
 __device__ __forceinline__ float lane_bcast(float v, int l) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }

@@ -693,13 +693,27 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
     const int bp1 = bp + 1;
     const int NB = bp / 16;
     const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int li = lane & 15, lk = lane >> 4;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    int lane = tid & 63;
+    int li = lane & 15, lk = lane >> 4;
     const int nblk = (Mx + 15) / 16;
     const cplx<T> zero = {T(0), T(0)};
     // this lane's panel row, relative to p0
-    const bool own = lane < 48;
-    const int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
+    bool own = lane < 48;
+    int rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
+    // the lane indices again at the start of every pass, through an opaque
+    // move: the lane conditions built on them (d >= 0, rrel > k, ...) are
+    // then formed inside the pass, not hoisted out of the pass loop as
+    // 64-bit scalar masks held across it, which the compiler spilled to
+    // vector lanes by the hundreds (about 500 scalar spills; 4-5% of the
+    // factor's time.  The two-panel kernel measured slower with it.)
+    auto lane_indices = [&]() {
+        lane = opaque_int(tid & 63);
+        li = lane & 15;
+        lk = lane >> 4;
+        own = lane < 48;
+        rrel = lane < 16 ? lane : 16 + 32 * wave + (lane - 16);
+    };
 
     // entry (p0 + rrel, p0 + c) of the band, clamped address, and whether it exists
     auto ent_on = [&](int p0, int c, int nrow) {
@@ -726,6 +740,7 @@ __device__ __forceinline__ void panel_factor_system(cplx<T>* __restrict__ base, 
     prefetch(0, nblk > 0 ? 16 + 16 * min(NB, reach[0]) : 0, 0);
 
     for (int q = 0; q < nblk; ++q) {
+        lane_indices();
         const int p0 = 16 * q;
         const int nb = min(16, Mx - p0);
         const int nr = min(NB, reach[q]);
