@@ -106,12 +106,24 @@ __global__ void __launch_bounds__(128) band_diag_inverse_kernel(const cplx<T>* _
 // the real and imaginary slots of one complex sweep: every operand's real
 // part is A's, its imaginary part B's, and the products drop the cross
 // terms.  Both imaginary parts of the result are written as zeros.
+// STAGE (the FP32 backward sweep): the factor operands of a step, block row
+// c of L (16-entry pieces of the 256 columns it spans), are loaded with 16
+// consecutive lanes on each piece (4 pieces per load, whole cache lines)
+// and go through LDS (QB, two buffers by step parity, k XOR n swizzled so
+// that both the writes and the operand reads are free of bank conflicts)
+// into the MFMA layout.  Loaded in that layout directly, each load touched
+// 64 columns: 25.3 ms against 18.1 ms for the same bytes in pieces
+// (timing variants on synthetic storage of the L-shape N_t = 1024 shape).
+template <typename T, bool FWD>
+constexpr bool tile_stage() { return !FWD && sizeof(T) == 4; }
+
 template <typename T, bool FWD, int S, int NSET, bool PAIR>
 __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, const cplx<T>* __restrict__ LI,
                                                 int Mx, int bp, int nsys, int nrhs, const T* __restrict__ Vin,
                                                 T* __restrict__ Vout, int sys, int sysB,
                                                 const int* __restrict__ reach, T (*XR)[TB][XS], T (*XI)[TB][XS],
-                                                T (*YR)[TB][XS], T (*YI)[TB][XS]) {
+                                                T (*YR)[TB][XS], T (*YI)[TB][XS], cplx<T>* __restrict__ QB) {
+    constexpr bool STAGE = tile_stage<T, FWD>();
     using V4 = typename vec4<T>::type;
     const int bp1 = bp + 1;
     const int NB = bp / TB;
@@ -235,11 +247,25 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
     auto fetch = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2]) {
         const int c = FWD ? s : nblk - 1 - s;
         const int delta = FWD ? ((w - c - 1) & 3) + 1 : ((c - w - 1) & 3) + 1;
+        if constexpr (STAGE) {
+            // piece (jrel, nn): column 16 (c - 1 - jrel) + nn of block row
+            // c, entry kq (row 16 c + kq) by lane kq of a group of 16; the
+            // wave takes pieces 16 S w .. 16 S (w + 1) - 1, 4 per load, the
+            // set's 4 S slots reused as a flat array
 #pragma unroll
-        for (int t = 0; t < S; ++t) {
-            const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
+            for (int r = 0; r < 4 * S; ++r) {
+                const int colidx = (w * 4 * S + r) * 4 + (lane >> 4);
+                const int jb = c - 1 - (colidx >> 4), nn = colidx & 15, kq = lane & 15;
+                const int i = (TB * jb + nn) * bp1 + TB * (c - jb) + kq - nn;
+                qx[r >> 2][r & 3] = load_op(base, baseB, (uint32_t)min(max(i, 0), qlast));  // raw: masked where used
+            }
+        } else {
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) qx[t][kk] = load_op(base, baseB, q_index(j, c, kk));  // raw: masked where used
+            for (int t = 0; t < S; ++t) {
+                const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) qx[t][kk] = load_op(base, baseB, q_index(j, c, kk));  // raw: masked where used
+            }
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) px[kk] = load_op(libase, libaseB, li_addr(c, kk));
@@ -261,6 +287,17 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
         const int c = FWD ? s : nblk - 1 - s;
         const int par = s & 1;
         if (s < nblk) {
+            if constexpr (STAGE) {
+                // this step's pieces of block row c to QB[par] (read after
+                // the step's barrier; the buffer's previous readers, step
+                // s - 2, all passed step s - 1's barrier before this)
+#pragma unroll
+                for (int r = 0; r < 4 * S; ++r) {
+                    const int colidx = (w * 4 * S + r) * 4 + (lane >> 4);
+                    const int jrel = colidx >> 4, nn = colidx & 15, kq = lane & 15;
+                    QB[((par * 4 * S + jrel) * TB + nn) * TB + (kq ^ nn)] = qx[r >> 2][r & 3];
+                }
+            }
             if ((c & 3) == w) {
                 // ---- owner: x_c = P_c acc[0], to LDS for every wave
 #pragma unroll
@@ -340,6 +377,18 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
             for (int t = 0; t < S; ++t) {
                 const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
                 if (couples(j, c)) {
+                    // operands: this wave's registers, or QB (STAGE: entry
+                    // k = 4 kk + g of column n of block j = c - 1 - jrel)
+                    cplx<T> q[4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) {
+                        if constexpr (STAGE) {
+                            const int jrel = c - 1 - j, k = kof(kk);
+                            q[kk] = QB[((par * 4 * S + jrel) * TB + n) * TB + (k ^ n)];
+                        } else {
+                            q[kk] = qx[t][kk];
+                        }
+                    }
                     // masks only where some entry can fall outside: the
                     // last tile of the band, the last (ragged) column block
                     const bool edge = (FWD ? j - c : c - j) == NB || (FWD ? c : j) == nblk - 1;
@@ -347,13 +396,13 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
 #pragma unroll
                         for (int kk = 0; kk < 4; ++kk) {
                             const bool on = q_on(j, c, kk);
-                            qx[t][kk].re = on ? qx[t][kk].re : T(0);
-                            qx[t][kk].im = on ? qx[t][kk].im : T(0);
+                            q[kk].re = on ? q[kk].re : T(0);
+                            q[kk].im = on ? q[kk].im : T(0);
                         }
                     }
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) {
-                        const cplx<T> a = qx[t][kk];
+                        const cplx<T> a = q[kk];
                         // br + i bi = -x, pi = Im x: acc += Q (-x)
                         if constexpr (PAIR) {
                             accR[t] = mfma16x16x4<T>(a.re, br[kk], accR[t]);
@@ -392,14 +441,15 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
     if (gate && *gate) return;
     __shared__ T XR[NWAVE][TB][XS], XI[NWAVE][TB][XS];    // owner's tile in operand layout
     __shared__ T YR[2][TB][XS], YI[2][TB][XS];            // solved block, by step parity
+    __shared__ cplx<T> QB[tile_stage<T, FWD>() ? 2 * 4 * S * TB * TB : 1];   // staged factor operands
     const int x = blockIdx.x;
     if (x < ncplx) {
         tile_sweep_body<T, FWD, S, NSET, false>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, sys0 + x, sys0 + x, reach,
-                                                XR, XI, YR, YI);
+                                                XR, XI, YR, YI, QB);
     } else {
         const int a = sys0 + ncplx + 2 * (x - ncplx);
         const int b = a + 1 < sys0 + nrun ? a + 1 : a;
-        tile_sweep_body<T, FWD, S, NSET, true>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, a, b, reach, XR, XI, YR, YI);
+        tile_sweep_body<T, FWD, S, NSET, true>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, a, b, reach, XR, XI, YR, YI, QB);
     }
 }
 
@@ -420,8 +470,10 @@ template <typename T, bool FWD, int S>
 static hipError_t launch_tile_t(const void* LB, const void* LI, const int* reach, int Mx, int bp, int nsys, int nrhs,
                                 const void* Vin, void* Vout, hipStream_t st, int sys0, int nrun, int nreal) {
     // register sets (prefetch distance NSET - 1 steps): measured best at
-    // 3 for FP32 and 2 for FP64 (whose third set costs occupancy)
-    constexpr int NSET = sizeof(T) == 4 ? 3 : 2;
+    // 3 for the FP32 forward sweep and 2 for FP64 (whose third set costs
+    // occupancy); 2 for the staged FP32 backward sweep, whose third set
+    // would spill
+    constexpr int NSET = (sizeof(T) == 4 && FWD) ? 3 : 2;
     const int ncplx = nrun - nreal;
     dim3 grid(ncplx + (nreal + 1) / 2, (nrhs + TB - 1) / TB);
     hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET>), grid, dim3(256), 0, st,
