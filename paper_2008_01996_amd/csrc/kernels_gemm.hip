@@ -405,7 +405,10 @@ size_t gemm_resid_partials(int M, int N, int batch) {
 // time columns: the row's CSR entries (up to NNZ of them in registers, a
 // longer row loops over the rest) are read once and serve both products;
 // for a fixed time column the lanes of a wave read consecutive rows of U.
-constexpr int SPATIAL_KC = 16;
+// KC = 64: the CSR arrays (6.8 MB at M_x = 48641) are read once per 64
+// time columns of a right-hand side (16 measured 8.6 ms against 7.7 ms at
+// the L-shape N_t = 1024 shape, 16 right-hand sides).
+constexpr int SPATIAL_KC = 64;
 
 template <int NNZ>
 __global__ void __launch_bounds__(256) spatial_apply_kernel(int Mx, int Nt, int nrhs, const int* __restrict__ rowptr,
