@@ -50,8 +50,8 @@ FP64_STAGES_IN_FP32_FORM = ("fwd1", "back", "resid")
 TRAFFIC = {
     # band_ldl_reg_kernel, square128_nt256: FETCH 1.186736e6 KiB x 1.9998 + WRITE 2.081217e6 KiB x 1.0
     ("square128_nt256", "band_ldl"): {"source_sha256": "a38814f1e66c0f7c7c10127a076270df2baa650bdea745c7344342f5f16ba042", "bytes_per_launch": 4.5613e+09},
-    # gemm_wide_kernel<double, 3> (FP64 residual), lshape128_nt1024: FETCH 2.5334e7 KiB x 1.9997 + WRITE 7.3064e6 KiB x 1.0
-    ("lshape128_nt1024", "resid"): {"source_sha256": "717f53ed820733213be851698d9e82764c53977ffcf88207a97d7c9b9955f85f", "bytes_per_launch": 5.9357e+10},
+    # gemm_wide_kernel<double, 3> (FP64 residual), lshape128_nt1024: FETCH 2.5326e7 KiB x 1.9997 + WRITE 7.3157e6 KiB x 1.0
+    ("lshape128_nt1024", "resid"): {"source_sha256": "1458280d49e4b0e582c2c9a75c34bc321dc9ced6ccba149fd02a79d5989da00f", "bytes_per_launch": 5.9351e+10},
 }
 
 WORKLOADS = {
