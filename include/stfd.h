@@ -87,7 +87,7 @@ typedef struct {
     double rtol;          /* target ||F~ - K_h u||_2 / ||F~||_2 (default 1e-10) */
     int max_refine;       /* maximum number of refinement corrections (default 30) */
     int method;           /* STFD_METHOD_FD (default) or STFD_METHOD_BSC */
-    int inner_refine;     /* FD only, 0 to 3: steps of refinement of the spatial
+    int inner_refine;     /* FD only, -1 to 3: steps of refinement of the spatial
                              solves inside each application.  With k > 0, G is
                              kept in FP64, solved once by the band factors and
                              then k times on its residual g_k - (M_x + lambda_k
@@ -98,7 +98,10 @@ typedef struct {
                              FP32 form then needs fp64_transforms bits 0 and 2
                              (STFD_EINVAL otherwise).  Costs one pair of sweeps
                              per step and 2 x 8 M_x x 2 n_sys bytes per
-                             right-hand side of device memory.  Default 0. */
+                             right-hand side of device memory.  Default -1
+                             (automatic): 1 in the FP32 form with the FP64
+                             transforms (and 2 in the first application, see
+                             inner_refine_first), 0 otherwise. */
     int graph;            /* FD only: 1 = the refinement rounds of stfd_fd_solve and
                              stfd_batch_solve run as captured HIP graphs
                              (apply, residual and a device-side convergence check;
@@ -112,6 +115,15 @@ typedef struct {
                              work buffers for this many right-hand sides, so that
                              factor and solve allocate nothing (up to nrhs_max
                              right-hand sides).  Default 0: allocated on first use. */
+    int inner_refine_first; /* FD only, -1 to 3: inner_refine for an application to
+                             the load itself (the first of a solve, and
+                             stfd_fd_apply); the later applications, to a
+                             residual, take inner_refine.  -1 (default): the
+                             same as inner_refine, or with inner_refine -1 the
+                             automatic choice (2 in the FP32 form).  The first application's
+                             error is the rough one the FP32 rounding leaves on
+                             the whole solution, the later ones' only on a
+                             correction, so the first can take more steps. */
 } stfd_opts;
 
 typedef struct {
@@ -418,13 +430,15 @@ size_t stfd_kh_residual_noalloc_max_bytes(void);
  * STFD_ST_FWD2 (forward transforms), STFD_ST_SWEEP_FWD, STFD_ST_SWEEP_BWD,
  * STFD_ST_BACK (back transform and update), STFD_ST_SPATIAL, STFD_ST_RESID,
  * STFD_ST_REDUCE (FP64 residual), STFD_ST_INNER (residual and update of the
- * spatial solves' inner refinement; its sweeps count as sweeps).
+ * spatial solves' inner refinement; its sweeps count as sweeps),
+ * STFD_ST_BAND_INV (inverses of the factor's diagonal blocks, for the tile
+ * sweeps).
  * stfd_profile(p, 1) enables and clears the accumulators, (p, 0) disables.
  * stfd_profile_read waits for the recorded events and returns, per stage, the
  * summed milliseconds and the number of launches since the last clear
  * (ms, counts: STFD_NSTAGE entries each, caller-owned).
  * ------------------------------------------------------------------------- */
-#define STFD_NSTAGE 11
+#define STFD_NSTAGE 12
 #define STFD_ST_BAND_INIT 0
 #define STFD_ST_BAND_LDL 1
 #define STFD_ST_FWD1 2
@@ -436,6 +450,7 @@ size_t stfd_kh_residual_noalloc_max_bytes(void);
 #define STFD_ST_RESID 8
 #define STFD_ST_REDUCE 9
 #define STFD_ST_INNER 10
+#define STFD_ST_BAND_INV 11
 int stfd_profile(stfd_problem* p, int enable);
 int stfd_profile_read(stfd_problem* p, double* ms, long long* counts);
 

@@ -32,9 +32,10 @@ extern "C" int stfd_opts_default(stfd_opts* o) {
     o->rtol = 1e-10;
     o->max_refine = 30;
     o->method = STFD_METHOD_FD;
-    o->inner_refine = 0;
+    o->inner_refine = -1;
     o->graph = 1;
     o->nrhs_max = 0;
+    o->inner_refine_first = -1;
     return STFD_OK;
 }
 

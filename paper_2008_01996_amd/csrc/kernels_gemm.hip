@@ -479,9 +479,14 @@ hipError_t launch_spatial_apply(int Mx, int Nt, int nrhs, const int* rowptr, con
 // the subtraction in FP64 from FP64 G and Z, R rounded to the working
 // precision (the band factors solve it).  Layout of G, Z, R per RHS:
 // column-major M_x x 2 n_sys, real parts of system k in column k, imaginary
-// parts in column n_sys + k.  One thread per row; grid.y runs over the
-// systems, grid.z over the right-hand sides.
-template <typename TR>
+// parts in column n_sys + k.  A thread takes one row and RESID_KS systems:
+// the row's CSR entries (up to NNZ in registers) are read once for all of
+// them (one system per thread read them once per system: 8 thousand times
+// at the L-shape N_t = 1024 shape with 16 right-hand sides).  grid.y runs
+// over the groups of systems, grid.z over the right-hand sides.
+constexpr int RESID_KS = 32;
+
+template <typename TR, int NNZ>
 __global__ void __launch_bounds__(256) spatial_resid_kernel(int Mx, int nsys, const int* __restrict__ rowptr,
                                                             const int* __restrict__ col,
                                                             const double* __restrict__ valM,
@@ -493,29 +498,48 @@ __global__ void __launch_bounds__(256) spatial_resid_kernel(int Mx, int nsys, co
     if (gate && *gate) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Mx) return;
-    const int k = blockIdx.y;
-    const size_t rhs = (size_t)blockIdx.z * 2 * nsys * Mx;
-    const size_t cr = rhs + (size_t)k * Mx, ci = rhs + (size_t)(nsys + k) * Mx;
-    const double lr = lam[2 * k], li = lam[2 * k + 1];
-    double sr = 0.0, si = 0.0;
-    for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-        const int j = col[e];
-        const double mr = valM[e] + lr * valA[e], mi = li * valA[e];
-        const double xr = Z[cr + j], xi = Z[ci + j];
-        sr += mr * xr - mi * xi;
-        si += mr * xi + mi * xr;
+    const int e0 = rowptr[i], n = rowptr[i + 1] - e0;
+    int c[NNZ];
+    double vm[NNZ], va[NNZ];
+#pragma unroll
+    for (int e = 0; e < NNZ; ++e) {
+        const bool on = e < n;
+        c[e] = on ? col[e0 + e] : i;
+        vm[e] = on ? valM[e0 + e] : 0.0;
+        va[e] = on ? valA[e0 + e] : 0.0;
     }
-    R[cr + i] = static_cast<TR>(G[cr + i] - sr);
-    R[ci + i] = static_cast<TR>(G[ci + i] - si);
+    const size_t rhs = (size_t)blockIdx.z * 2 * nsys * Mx;
+    const int k0 = blockIdx.y * RESID_KS, k1 = min(k0 + RESID_KS, nsys);
+    for (int k = k0; k < k1; ++k) {
+        const size_t cr = rhs + (size_t)k * Mx, ci = rhs + (size_t)(nsys + k) * Mx;
+        const double lr = lam[2 * k], li = lam[2 * k + 1];
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int e = 0; e < NNZ; ++e) {
+            const double mr = vm[e] + lr * va[e], mi = li * va[e];
+            const double xr = Z[cr + c[e]], xi = Z[ci + c[e]];
+            sr += mr * xr - mi * xi;
+            si += mr * xi + mi * xr;
+        }
+        for (int e = NNZ; e < n; ++e) {
+            const int j = col[e0 + e];
+            const double mr = valM[e0 + e] + lr * valA[e0 + e], mi = li * valA[e0 + e];
+            const double xr = Z[cr + j], xi = Z[ci + j];
+            sr += mr * xr - mi * xi;
+            si += mr * xi + mi * xr;
+        }
+        R[cr + i] = static_cast<TR>(G[cr + i] - sr);
+        R[ci + i] = static_cast<TR>(G[ci + i] - si);
+    }
 }
 
 template <typename TR>
 hipError_t launch_spatial_resid(int Mx, int nsys, int nrhs, const int* rowptr, const int* col, const double* valM,
                                 const double* valA, const double* lam, const double* G, const double* Z, void* R,
                                 hipStream_t st) {
-    dim3 grid((Mx + 255) / 256, nsys, nrhs);
-    hipLaunchKernelGGL(spatial_resid_kernel<TR>, grid, dim3(256), 0, st, Mx, nsys, rowptr, col, valM, valA, lam, G,
-                       Z, static_cast<TR*>(R), launch_gate());
+    dim3 grid((Mx + 255) / 256, (nsys + RESID_KS - 1) / RESID_KS, nrhs);
+    hipLaunchKernelGGL((spatial_resid_kernel<TR, 8>), grid, dim3(256), 0, st, Mx, nsys, rowptr, col, valM, valA,
+                       lam, G, Z, static_cast<TR*>(R), launch_gate());
     return hipGetLastError();
 }
 

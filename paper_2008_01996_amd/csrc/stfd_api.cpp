@@ -240,6 +240,13 @@ void fill_report(const Decomp& D, stfd_setup_report* r) {
     r->n_sys = D.npair + D.nreal;
 }
 
+// steps of the inner refinement in an application to the load (first) or to
+// a residual
+int inner_steps(const stfd_problem* p, bool first) {
+    return first && p->opts.inner_refine_first >= 0 ? p->opts.inner_refine_first : p->opts.inner_refine;
+}
+bool inner_any(const stfd_problem* p) { return inner_steps(p, true) > 0 || inner_steps(p, false) > 0; }
+
 int ensure_work(stfd_problem* p, int nrhs) {
     if (nrhs <= p->nrhs_cap) return STFD_OK;
     drop_graphs(p);                     // captured rounds refer to the old buffers
@@ -250,8 +257,8 @@ int ensure_work(stfd_problem* p, int nrhs) {
     struct { void** ptr; size_t bytes; } req[] = {
         {&p->d_T1, p->fwd_merged ? 0 : Mx * 2 * Nt * es * nrhs},
         {&p->d_G, Mx * 2 * ns * es * nrhs},
-        {reinterpret_cast<void**>(&p->d_Gs), p->opts.inner_refine > 0 ? Mx * 2 * ns * 8 * nrhs : 0},
-        {reinterpret_cast<void**>(&p->d_Z64), p->opts.inner_refine > 0 ? Mx * 2 * ns * 8 * nrhs : 0},
+        {reinterpret_cast<void**>(&p->d_Gs), inner_any(p) ? Mx * 2 * ns * 8 * nrhs : 0},
+        {reinterpret_cast<void**>(&p->d_Z64), inner_any(p) ? Mx * 2 * ns * 8 * nrhs : 0},
         {reinterpret_cast<void**>(&p->d_P), Mx * 2 * Nt * 8 * nrhs},
         {reinterpret_cast<void**>(&p->d_R), Mx * Nt * 8 * nrhs},
         {reinterpret_cast<void**>(&p->d_part), parts * 2 * 8},
@@ -535,9 +542,18 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
     if (opts) o = *opts;
     if ((o.precision != STFD_PREC_FP32 && o.precision != STFD_PREC_FP64) || !(o.rtol >= 0.0) || o.max_refine < 0 ||
         o.max_refine >= STFD_MAX_HIST || o.fp64_transforms < 0 || o.fp64_transforms > 7 ||
-        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC) || o.inner_refine < 0 || o.inner_refine > 3 ||
-        o.graph < 0 || o.graph > 1 || o.nrhs_max < 0)
+        (o.method != STFD_METHOD_FD && o.method != STFD_METHOD_BSC) || o.inner_refine < -1 || o.inner_refine > 3 ||
+        o.inner_refine_first < -1 || o.inner_refine_first > 3 || o.graph < 0 || o.graph > 1 || o.nrhs_max < 0)
         return fail(STFD_EINVAL, "fd_setup: bad options");
+    // automatic inner refinement: in the FP32 form of Algorithm FD with FP64
+    // transforms, two steps in the application to the load and one in each
+    // later one (the L-shape N_t = 1024 solve: 3 applications instead of 5,
+    // 800 against 903 ms); none otherwise
+    if (o.inner_refine < 0) {
+        const bool fp32_fd = o.method == STFD_METHOD_FD && o.precision == STFD_PREC_FP32 && (o.fp64_transforms & 5) == 5;
+        o.inner_refine = fp32_fd ? 1 : 0;
+        if (o.inner_refine_first < 0) o.inner_refine_first = fp32_fd ? 2 : 0;
+    }
     {
         const int bp = std::max(16, (space->half_band + 15) / 16 * 16);
         if (bp > stfd::BAND_BPMAX)
@@ -545,9 +561,10 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
                                          " of the spatial matrices exceeds " + std::to_string(stfd::BAND_BPMAX) +
                                          ", the largest the substitution sweeps take");
     }
-    if (o.method == STFD_METHOD_BSC && o.inner_refine != 0)
+    const bool inner_on = o.inner_refine > 0 || o.inner_refine_first > 0;
+    if (o.method == STFD_METHOD_BSC && inner_on)
         return fail(STFD_EINVAL, "fd_setup: the inner refinement belongs to Algorithm FD");
-    if (o.precision == STFD_PREC_FP32 && o.inner_refine != 0 && (o.fp64_transforms & 5) != 5)
+    if (o.precision == STFD_PREC_FP32 && inner_on && (o.fp64_transforms & 5) != 5)
         return fail(STFD_EINVAL, "fd_setup: the inner refinement keeps G and Z in FP64, so the FP32 form needs the "
                                  "FP64 forward and back transforms (fp64_transforms bits 0 and 2)");
     if (o.method == STFD_METHOD_BSC) return bs_setup(space, Nt, At, Mt, o, static_cast<hipStream_t>(hip_stream), out);
@@ -783,7 +800,7 @@ extern "C" int stfd_fd_factor(stfd_problem* p, void* hip_stream) {
                "band LDL^T");
     }
     if (tiles) {
-        StageTimer tm(p, STFD_ST_BAND_LDL, st);
+        StageTimer tm(p, STFD_ST_BAND_INV, st);
         HIPCHK(f32 ? stfd::launch_band_diag_inverse<float>(p->d_LB, p->d_LI, p->Mx, p->bp, p->nsys, st)
                    : stfd::launch_band_diag_inverse<double>(p->d_LB, p->d_LI, p->Mx, p->bp, p->nsys, st),
                "diagonal block inverses");
@@ -848,13 +865,15 @@ hipError_t launch_gemm_tuned(const stfd_problem* p, stfd::GemmKind kind, const s
     return stfd::launch_gemm(kind, g, st);
 }
 
-int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st);
+int fd_apply_rest(stfd_problem* p, int nrhs, double* U, int nin, hipStream_t st);
 
 // one FD application: X (FP64 residual or load, Mx x Nt per RHS) -> U += alpha FD(X)
 int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t st) {
     const bool f32 = is_fp32(p);
     const int Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
-    const bool inner = p->opts.inner_refine > 0;
+    // an application to anything but the residual buffer is one to a load
+    const int nin = inner_steps(p, X != p->d_R);
+    const bool inner = nin > 0;
     const int mask = f32 ? p->opts.fp64_transforms : 7;
     stfd::GemmArgs g{};
     if (p->fwd_merged) {
@@ -870,7 +889,7 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
             HIPCHK(launch_gemm_tuned(p, f32 && !inner ? stfd::GEMM_D_D_STORE_F : stfd::GEMM_D_D_STORE_D, g, st),
                    "forward transform");
         }
-        return fd_apply_rest(p, nrhs, U, st);
+        return fd_apply_rest(p, nrhs, U, nin, st);
     }
     // step 2a: T1 = X W1   (Mx x 2Nt)
     g.A = X;
@@ -900,18 +919,18 @@ int fd_apply(stfd_problem* p, int nrhs, const double* X, double* U, hipStream_t 
                                  g, st),
                "forward transform 2");
     }
-    return fd_apply_rest(p, nrhs, U, st);
+    return fd_apply_rest(p, nrhs, U, nin, st);
 }
 
 // steps 3 and 4 of an FD application with the refinement of the spatial
 // solves: G (FP64, in Gs) is solved once by the band factors, the solution
-// kept in FP64 (Z64); then, opts.inner_refine times, R = G - (M_x + lambda_k
+// kept in FP64 (Z64); then, nin times, R = G - (M_x + lambda_k
 // A_x) Z64 in FP64, solved by the same factors and added to Z64; finally
 // U += Re(Z64 Xb) in FP64.  In the FP32 form G is rounded to FP32 for the
 // factors and every solution widened back, so neither G's nor Z's FP32
 // rounding stays in the result: only the factors' error, which each step
 // contracts.
-int fd_apply_inner(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
+int fd_apply_inner(stfd_problem* p, int nrhs, double* U, int nin, hipStream_t st) {
     const bool f32 = is_fp32(p);
     const int Mx = p->Mx, ns = p->nsys;
     const size_t n = (size_t)Mx * 2 * ns * nrhs;
@@ -929,7 +948,7 @@ int fd_apply_inner(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
         rc = spatial_sweeps(p, nrhs, p->d_Gs, p->d_Z64, st, true);
         if (rc) return rc;
     }
-    for (int s = 0; s < p->opts.inner_refine; ++s) {
+    for (int s = 0; s < nin; ++s) {
         {
             StageTimer tm(p, STFD_ST_INNER, st);
             HIPCHK(f32 ? stfd::launch_spatial_resid<float>(Mx, ns, nrhs, p->d_rowptr, p->d_col, p->d_valM, p->d_valA,
@@ -958,13 +977,12 @@ int fd_apply_inner(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
 }
 
 // steps 3 and 4 of an FD application, from G to U += Re(Z Xb)
-int fd_apply_rest(stfd_problem* p, int nrhs, double* U, hipStream_t st) {
+int fd_apply_rest(stfd_problem* p, int nrhs, double* U, int nin, hipStream_t st) {
     const bool f32 = is_fp32(p);
     const int Mx = p->Mx, Nt = p->Nt, ns = p->nsys;
-    const bool inner = p->opts.inner_refine > 0;
     const int mask = f32 ? p->opts.fp64_transforms : 7;
     stfd::GemmArgs g{};
-    if (inner) return fd_apply_inner(p, nrhs, U, st);
+    if (nin > 0) return fd_apply_inner(p, nrhs, U, nin, st);
     // step 3: spatial solves, in place in G
     int rc = spatial_sweeps(p, nrhs, p->d_G, p->d_G, st, true);
     if (rc) return rc;

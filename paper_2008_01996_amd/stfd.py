@@ -31,7 +31,7 @@ EXPORTED = [
 ]
 
 STAGES = ["band_init", "band_ldl", "fwd1", "fwd2", "sweep_fwd", "sweep_bwd", "back", "spatial", "resid",
-          "reduce", "inner"]
+          "reduce", "inner", "band_inv"]
 
 
 class StfdError(RuntimeError):
@@ -43,7 +43,7 @@ class StfdError(RuntimeError):
 class Opts(C.Structure):
     _fields_ = [("precision", C.c_int), ("fp64_transforms", C.c_int), ("rtol", C.c_double),
                 ("max_refine", C.c_int), ("method", C.c_int), ("inner_refine", C.c_int),
-                ("graph", C.c_int), ("nrhs_max", C.c_int)]
+                ("graph", C.c_int), ("nrhs_max", C.c_int), ("inner_refine_first", C.c_int)]
 
 
 class Tuning(C.Structure):
@@ -292,13 +292,14 @@ class Problem:
     """Space-time solver (Algorithm FD, or BSc) for one (space, time mesh) pair on the current GPU."""
 
     def __init__(self, space: Space, At, Mt, precision="fp32", fp64_transforms=5, rtol=1e-10, max_refine=30,
-                 stream=None, method="fd", inner_refine=0, graph=True, nrhs_max=0,
+                 stream=None, method="fd", inner_refine=-1, graph=True, nrhs_max=0, inner_refine_first=-1,
                  tuning="cache"):
         """fp64_transforms (FP32 form only): bit mask of the transform GEMMs run
         on FP64 matrix cores, bit 0 first forward, bit 1 second forward, bit 2
         back transform.  method "fd" (Algorithm FD) or "bsc" (Algorithm BSc,
         Bartels-Stewart with the complex Schur form; precision "fp64").
-        inner_refine, graph, nrhs_max: the stfd_opts fields of those names.
+        inner_refine, graph, nrhs_max, inner_refine_first: the stfd_opts fields
+        of those names.
         tuning: kernel variants, "cache" (the autotuner's entry for this
         shape, if any), None (library defaults) or a dict of stfd_tuning
         fields."""
@@ -315,6 +316,7 @@ class Problem:
         o.max_refine = int(max_refine)
         o.method = {"fd": METHOD_FD, "bsc": METHOD_BSC}[method]
         o.inner_refine = int(inner_refine)
+        o.inner_refine_first = int(inner_refine_first)
         o.graph = int(bool(graph))
         o.nrhs_max = int(nrhs_max)
         self.precision = precision

@@ -4,8 +4,9 @@ factors and k more times on its FP64 residual g_k - (M_x + lambda_k A_x) z_k
 (Alg. FD step 3), the solutions summed in FP64 before the FP64 back
 transform.  Checked against the oracle's direct solve of K_h (Sec. 3.1) on a
 graded time mesh (kappa_2(X_t) large, so the spatial errors are amplified),
-both precisions, one and two inner steps, in captured rounds and launched one
-by one (bitwise the same), and the FP32 form's option checks."""
+both precisions, one and two inner steps (in every application, or a separate
+count for the application to the load), in captured rounds and launched one
+by one (bitwise the same), and the option checks."""
 import numpy as np
 import pytest
 
@@ -34,10 +35,10 @@ def _case():
     return _CACHE
 
 
-def _solve(c, precision, inner, graph=True):
+def _solve(c, precision, inner, graph=True, first=-1):
     sp = stfd.Space(c["mesh"])
     prob = stfd.Problem(sp, c["At"], c["Mt"], precision=precision, rtol=1e-11, max_refine=30, inner_refine=inner,
-                        graph=graph)
+                        graph=graph, inner_refine_first=first)
     prob.factor()
     F = torch.from_numpy(np.ascontiguousarray(np.stack([f.T for f in c["Fs"]]))).to("cuda:0")
     U = torch.empty_like(F)
@@ -47,11 +48,13 @@ def _solve(c, precision, inner, graph=True):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-@pytest.mark.parametrize("inner", [1, 2])
-def test_inner_refinement_matches_oracle(precision, inner):
+@pytest.mark.parametrize("inner,first", [(1, -1), (2, -1), (1, 2), (0, 2)])
+def test_inner_refinement_matches_oracle(precision, inner, first):
+    """inner steps in every application, or first steps in the application
+    to the load and inner in those to a residual"""
     c = _case()
     rep0, _ = _solve(c, precision, 0)
-    rep, U = _solve(c, precision, inner)
+    rep, U = _solve(c, precision, inner, first=first)
     Uh = U.cpu().numpy()
     assert rep["converged"], rep
     for q, Fq in enumerate(c["Fs"]):
@@ -61,7 +64,7 @@ def test_inner_refinement_matches_oracle(precision, inner):
         assert err <= 1e-10 and res <= 1e-10, (q, err, res)
     # the spatial solves only get more accurate: never more applications
     assert rep["iterations"] <= rep0["iterations"]
-    print(f"  {precision} inner {inner}: applications {rep['iterations']} (without: {rep0['iterations']}), "
+    print(f"  {precision} inner {inner} first {first}: applications {rep['iterations']} (without: {rep0['iterations']}), "
           f"history {rep['rel_residual']}", flush=True)
 
 
@@ -84,3 +87,8 @@ def test_inner_refinement_options():
             stfd.Problem(sp, c["At"], c["Mt"], precision="fp32", fp64_transforms=mask, inner_refine=1)
     with pytest.raises(stfd.StfdError):
         stfd.Problem(sp, c["At"], c["Mt"], precision="fp64", inner_refine=4)
+    for first in (-2, 4):
+        with pytest.raises(stfd.StfdError):
+            stfd.Problem(sp, c["At"], c["Mt"], precision="fp64", inner_refine_first=first)
+    with pytest.raises(stfd.StfdError):
+        stfd.Problem(sp, c["At"], c["Mt"], precision="fp32", fp64_transforms=1, inner_refine_first=1)
