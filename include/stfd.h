@@ -100,8 +100,9 @@ typedef struct {
                              per step and 2 x 8 M_x x 2 n_sys bytes per
                              right-hand side of device memory.  Default -1
                              (automatic): 1 in the FP32 form with the FP64
-                             transforms (and 2 in the first application, see
-                             inner_refine_first), 0 otherwise. */
+                             transforms and N_t >= 512 (and 2 in the first
+                             application, see inner_refine_first), 0
+                             otherwise. */
     int graph;            /* FD only: 1 = the refinement rounds of stfd_fd_solve and
                              stfd_batch_solve run as captured HIP graphs
                              (apply, residual and a device-side convergence check;

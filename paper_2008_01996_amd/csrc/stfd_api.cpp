@@ -546,11 +546,15 @@ extern "C" int stfd_fd_setup(const stfd_space* space, int Nt, const double* At, 
         o.inner_refine_first < -1 || o.inner_refine_first > 3 || o.graph < 0 || o.graph > 1 || o.nrhs_max < 0)
         return fail(STFD_EINVAL, "fd_setup: bad options");
     // automatic inner refinement: in the FP32 form of Algorithm FD with FP64
-    // transforms, two steps in the application to the load and one in each
-    // later one (the L-shape N_t = 1024 solve: 3 applications instead of 5,
-    // 800 against 903 ms); none otherwise
+    // transforms and N_t >= 512, two steps in the application to the load and
+    // one in each later one; none otherwise.  The steps cost sweeps and save
+    // applications, whose transform and residual GEMMs grow as N_t^2: the
+    // L-shape N_t = 1024 solve takes 3 applications instead of 5 (818 against
+    // 903 ms), the square N_t = 512 one 3 instead of 7 (485 against 518 ms),
+    // but the square N_t = 256 one (one right-hand side) 15.9 against 14.8 ms
     if (o.inner_refine < 0) {
-        const bool fp32_fd = o.method == STFD_METHOD_FD && o.precision == STFD_PREC_FP32 && (o.fp64_transforms & 5) == 5;
+        const bool fp32_fd = o.method == STFD_METHOD_FD && o.precision == STFD_PREC_FP32 &&
+                             (o.fp64_transforms & 5) == 5 && Nt >= 512;
         o.inner_refine = fp32_fd ? 1 : 0;
         if (o.inner_refine_first < 0) o.inner_refine_first = fp32_fd ? 2 : 0;
     }
