@@ -50,8 +50,8 @@ FP64_STAGES_IN_FP32_FORM = ("fwd1", "back", "resid")
 TRAFFIC = {
     # band_ldl_reg_kernel, square128_nt256: FETCH 1.186736e6 KiB x 1.9998 + WRITE 2.081217e6 KiB x 1.0
     ("square128_nt256", "band_ldl"): {"source_sha256": "a38814f1e66c0f7c7c10127a076270df2baa650bdea745c7344342f5f16ba042", "bytes_per_launch": 4.5613e+09},
-    # band_ldl_panel2_kernel<float> (FP32 factor), lshape128_nt1024: FETCH 8.1536e7 KiB x 1.9997 + WRITE 1.6985e8 KiB x 1.0
-    ("lshape128_nt1024", "band_ldl"): {"source_sha256": "50d43ecd1b5de45b3ec5d527d25aacbd1c54b6641a903be6c73eed92ed983765", "bytes_per_launch": 3.4089e+11},
+    # band_ldl_panel2_kernel<float> (FP32 factor), lshape128_nt1024: FETCH 8.2150e7 KiB x 1.9997 + WRITE 1.7078e8 KiB x 1.0
+    ("lshape128_nt1024", "band_ldl"): {"source_sha256": "91dc4aaac643c24a7fc8474be43884aa6e4a0f01e82a4d9b0ddb2f56b57f8e56", "bytes_per_launch": 3.4309e+11},
     # gemm_wide_kernel<double, 3> (FP64 residual), lshape128_nt1024: FETCH 2.5326e7 KiB x 1.9997 + WRITE 7.3157e6 KiB x 1.0
     ("lshape128_nt1024", "resid"): {"source_sha256": "1458280d49e4b0e582c2c9a75c34bc321dc9ced6ccba149fd02a79d5989da00f", "bytes_per_launch": 5.9351e+10},
 }
