@@ -17,10 +17,9 @@
 // factorization, band_diag_inverse_kernel), so it is one more tile product.
 //
 // Step for block c (one workgroup barrier):
-//   owner wave (c mod 4): its first tile is complete; it goes through LDS
-//     into the operand layout, is multiplied by L_cc^-1 (or L_cc^-T), the
-//     result is stored (forward: times D_c^-1) and written to LDS for the
-//     other waves; the owner's tiles move up one slot and the block that
+//   owner wave (c mod 4): its first tile is complete; it is multiplied by
+//     L_cc^-1 (or L_cc^-T) from its accumulator registers, the result is
+//     stored (forward: times D_c^-1) and written to LDS for the other waves; the owner's tiles move up one slot and the block that
 //     enters the window (c + 4S forward, c - 4S backward) takes the last;
 //   all waves: each pending tile j takes -= Q_jc x_c, Q_jc = L_jc (forward)
 //     or L_cj^T (backward), its operands loaded from the band storage
@@ -43,7 +42,6 @@ namespace stfd {
 namespace {
 
 constexpr int TB = 16;        // block size (rows, columns, right-hand sides)
-constexpr int NWAVE = 4;
 constexpr int XS = TB + 1;    // LDS row stride of the transposed tiles
 
 }  // namespace
@@ -117,12 +115,12 @@ __global__ void __launch_bounds__(128) band_diag_inverse_kernel(const cplx<T>* _
 template <typename T, bool FWD>
 constexpr bool tile_stage() { return !FWD && sizeof(T) == 4; }
 
-template <typename T, bool FWD, int S, int NSET, bool PAIR>
+template <typename T, bool FWD, int S, int NSET, bool VT, bool PAIR>
 __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, const cplx<T>* __restrict__ LI,
                                                 int Mx, int bp, int nsys, int nrhs, const T* __restrict__ Vin,
                                                 T* __restrict__ Vout, int sys, int sysB,
-                                                const int* __restrict__ reach, T (*XR)[TB][XS], T (*XI)[TB][XS],
-                                                T (*YR)[TB][XS], T (*YI)[TB][XS], cplx<T>* __restrict__ QB) {
+                                                const int* __restrict__ reach, T (*YR)[TB][XS], T (*YI)[TB][XS],
+                                                cplx<T>* __restrict__ QB) {
     constexpr bool STAGE = tile_stage<T, FWD>();
     using V4 = typename vec4<T>::type;
     const int bp1 = bp + 1;
@@ -184,6 +182,36 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
             ai[r] = on ? ai[r] : T(0);
         }
     };
+    // VT (FP32, M_x >= 4): the entering tile's rows 16 j + 4 g .. + 3 of
+    // a lane are consecutive, one 16-byte load per part (the columns are
+    // 4-byte aligned, which these loads allow) from row0c = clamp(row0, 0,
+    // M_x - 4), so that the four rows read stay inside the column; row r of
+    // the group is then element r + (row0 - row0c), taken where the tile is
+    // used (rows that the shift pushes past the vector are past M_x)
+    auto row0c_of = [&](int j) { return min(max(TB * j + 4 * g, 0), Mx - 4); };
+    auto load_tile_vec = [&](int j, V4& ar, V4& ai) {
+        const int r0c = row0c_of(j);
+        __builtin_memcpy(&ar, vin_re + r0c, sizeof(V4));
+        __builtin_memcpy(&ai, vin_im + r0c, sizeof(V4));
+    };
+    auto tile_take = [&](int j, V4& ar, V4& ai) {
+        if constexpr (VT) {
+            const int sh = TB * j + 4 * g - row0c_of(j);
+            const V4 br = ar, bi = ai;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                T vr = br[3], vi = bi[3];
+#pragma unroll
+                for (int q = 2; q >= r; --q) {
+                    vr = r + sh == q ? br[q] : vr;
+                    vi = r + sh == q ? bi[q] : vi;
+                }
+                ar[r] = vr;
+                ai[r] = vi;
+            }
+        }
+        tile_mask(j, ar, ai);
+    };
     auto load_tile = [&](int j, V4& ar, V4& ai) {
         load_tile_raw(j, ar, ai);
         tile_mask(j, ar, ai);
@@ -215,16 +243,19 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
         return d <= bp && col < Mx;
     };
     // whether block column c couples to block j (within the band and the
-    // envelope of the factor: reach[b] blocks below diagonal block b)
-    auto couples = [&](int j, int c) {
-        return FWD ? (j > c && j < nblk && j - c <= min(NB, reach[c]))
+    // envelope of the factor: reach[b] blocks below diagonal block b; the
+    // forward sweep's bound rc = min(NB, reach[c]) is read once per step)
+    auto couples = [&](int j, int c, int rc) {
+        return FWD ? (j > c && j < nblk && j - c <= rc)
                    : (j < c && j >= 0 && c - j <= min(NB, reach[j]));
     };
     // operand of the diagonal inverse for k-step kk: forward L_cc^-1[m][k],
-    // backward L_cc^-1[k][m]
+    // backward L_cc^-1[k][m], with k the row that accumulator register kk
+    // of the lane holds (the solve takes the owner's tile as it is, with
+    // no transposition through LDS)
     auto li_addr = [&](int c, int kk) -> uint32_t {
         const int cc = min(max(c, 0), nblk - 1);
-        const int m = n, k = 4 * kk + g;
+        const int m = n, k = mfma_row<T>(g, kk);
         return (uint32_t)(cc * TB * TB + (FWD ? k * TB + m : m * TB + k));
     };
 
@@ -236,12 +267,12 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
 
     // Everything step s needs from memory is loaded NSET - 1 steps ahead, at
     // the start of step s - NSET + 1 (so that the loads are in flight during
-    // that step's work), by every wave alike (so the counts of outstanding loads are the same on
-    // every path and the waits stay exact): the factor operands of the
-    // wave's pending tiles, the data the owner of block c needs (the
-    // diagonal inverse, the tile entering when c retires; the other waves
-    // load it too and drop it), and D of the rows of block c this wave
-    // stores (forward).
+    // that step's work): the factor operands of the wave's pending tiles,
+    // D of the rows of block c this wave stores (forward), and, by the
+    // owner of block c only, the diagonal inverse and the tile entering
+    // when c retires.  (Loaded by every wave alike, these two were three
+    // fifths of the cache lines a step requested, the vector memory
+    // front end the limit of the step's load issue.)
     cplx<T> qa[NSET][S][4], pa[NSET][4], da[NSET];
     V4 ea[NSET][2];
     auto fetch = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2]) {
@@ -267,16 +298,28 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
                 for (int kk = 0; kk < 4; ++kk) qx[t][kk] = load_op(base, baseB, q_index(j, c, kk));  // raw: masked where used
             }
         }
+        if ((c & 3) == w) {
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) px[kk] = load_op(libase, libaseB, li_addr(c, kk));
-        load_tile_raw(FWD ? c + 4 * S : c - 4 * S, ex[0], ex[1]);
+            for (int kk = 0; kk < 4; ++kk) px[kk] = load_op(libase, libaseB, li_addr(c, kk));
+            if constexpr (VT) load_tile_vec(FWD ? c + 4 * S : c - 4 * S, ex[0], ex[1]);
+            else load_tile_raw(FWD ? c + 4 * S : c - 4 * S, ex[0], ex[1]);
+        }
         if (FWD) {
             const int row = min(max(TB * c + 4 * w + g, 0), Mx - 1);
             dx = load_op(base, baseB, (uint32_t)(row * bp1));
         }
     };
+    // the sets go out in step order, each whole before the next: the waits
+    // before a set's use count the loads issued after it, and the count on
+    // entry to the loop (after these) bounds the count on every iteration.
+    // Left to the scheduler, the sets' loads were interleaved, the last
+    // load of set 0 came last, and every step then waited for its own
+    // fresh prefetch before its first product.
 #pragma unroll
-    for (int u = 0; u + 1 < NSET; ++u) fetch(u, qa[u], pa[u], da[u], ea[u]);
+    for (int u = 0; u + 1 < NSET; ++u) {
+        fetch(u, qa[u], pa[u], da[u], ea[u]);
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
     // one step: block c = (FWD ? s : nblk - 1 - s); steps past the end only fetch
     auto step = [&](int s, cplx<T> (&qx)[S][4], cplx<T> (&px)[4], cplx<T>& dx, V4 (&ex)[2],
@@ -287,6 +330,7 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
         const int c = FWD ? s : nblk - 1 - s;
         const int par = s & 1;
         if (s < nblk) {
+            const int rc = FWD ? min(NB, reach[c]) : NB;
             if constexpr (STAGE) {
                 // this step's pieces of block row c to QB[par] (read after
                 // the step's barrier; the buffer's previous readers, step
@@ -299,17 +343,14 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
                 }
             }
             if ((c & 3) == w) {
-                // ---- owner: x_c = P_c acc[0], to LDS for every wave
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    XR[w][mfma_row<T>(g, r)][n] = accR[0][r];
-                    XI[w][mfma_row<T>(g, r)][n] = accI[0][r];
-                }
-                wave_lds_sync();
+                // ---- owner: x_c = P_c acc[0], to LDS for every wave.  The
+                // products' k-step kk takes, in lane group g, the tile's row
+                // held in accumulator register kk (and the matching column
+                // of P_c): the sum runs over all 16 rows in another order
                 V4 xr = zero4<T>(), xi = zero4<T>();
 #pragma unroll
                 for (int kk = 0; kk < 4; ++kk) {
-                    const T br = XR[w][4 * kk + g][n], bi = XI[w][4 * kk + g][n];
+                    const T br = accR[0][kk], bi = accI[0][kk];
                     const cplx<T> a = px[kk];
                     if constexpr (PAIR) {
                         xr = mfma16x16x4<T>(a.re, br, xr);
@@ -333,7 +374,7 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
                     accI[t] = accI[t + 1];
                 }
                 V4 er = ex[0], ei = ex[1];
-                tile_mask(FWD ? c + 4 * S : c - 4 * S, er, ei);
+                tile_take(FWD ? c + 4 * S : c - 4 * S, er, ei);
                 accR[S - 1] = er;
                 accI[S - 1] = ei;
             }
@@ -376,7 +417,7 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
 #pragma unroll
             for (int t = 0; t < S; ++t) {
                 const int j = FWD ? c + delta + 4 * t : c - delta - 4 * t;
-                if (couples(j, c)) {
+                if (couples(j, c, rc)) {
                     // operands: this wave's registers, or QB (STAGE: entry
                     // k = 4 kk + g of column n of block j = c - 1 - jrel)
                     cplx<T> q[4];
@@ -431,7 +472,7 @@ __device__ __forceinline__ void tile_sweep_body(const cplx<T>* __restrict__ LB, 
 // Workgroups [0, ncplx): system sys0 + x, complex; workgroups past ncplx:
 // the real systems sys0 + ncplx + 2 (x - ncplx) and the next one (if any, else
 // the same system twice, its results written by both slots alike), paired.
-template <typename T, bool FWD, int S, int NSET>
+template <typename T, bool FWD, int S, int NSET, bool VT>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 2 : 1))) tile_sweep_kernel(const cplx<T>* __restrict__ LB,
                                                         const cplx<T>* __restrict__ LI, int Mx, int bp, int nsys,
                                                         int nrhs, const T* __restrict__ Vin, T* __restrict__ Vout,
@@ -439,17 +480,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof
                                                         const int* __restrict__ reach,
                                                         const int* __restrict__ gate) {
     if (gate && *gate) return;
-    __shared__ T XR[NWAVE][TB][XS], XI[NWAVE][TB][XS];    // owner's tile in operand layout
     __shared__ T YR[2][TB][XS], YI[2][TB][XS];            // solved block, by step parity
     __shared__ cplx<T> QB[tile_stage<T, FWD>() ? 2 * 4 * S * TB * TB : 1];   // staged factor operands
     const int x = blockIdx.x;
     if (x < ncplx) {
-        tile_sweep_body<T, FWD, S, NSET, false>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, sys0 + x, sys0 + x, reach,
-                                                XR, XI, YR, YI, QB);
+        tile_sweep_body<T, FWD, S, NSET, VT, false>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, sys0 + x, sys0 + x, reach,
+                                                YR, YI, QB);
     } else {
         const int a = sys0 + ncplx + 2 * (x - ncplx);
         const int b = a + 1 < sys0 + nrun ? a + 1 : a;
-        tile_sweep_body<T, FWD, S, NSET, true>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, a, b, reach, XR, XI, YR, YI, QB);
+        tile_sweep_body<T, FWD, S, NSET, VT, true>(LB, LI, Mx, bp, nsys, nrhs, Vin, Vout, a, b, reach, YR, YI, QB);
     }
 }
 
@@ -476,7 +516,18 @@ static hipError_t launch_tile_t(const void* LB, const void* LI, const int* reach
     constexpr int NSET = (sizeof(T) == 4 && FWD) ? 3 : 2;
     const int ncplx = nrun - nreal;
     dim3 grid(ncplx + (nreal + 1) / 2, (nrhs + TB - 1) / TB);
-    hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET>), grid, dim3(256), 0, st,
+    // the entering tile by 16-byte loads: FP32 (four consecutive rows per
+    // lane) with at least four rows
+    if constexpr (sizeof(T) == 4) {
+        if (Mx >= 4) {
+            hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET, true>), grid, dim3(256), 0, st,
+                               static_cast<const cplx<T>*>(LB), static_cast<const cplx<T>*>(LI), Mx, bp, nsys, nrhs,
+                               static_cast<const T*>(Vin), static_cast<T*>(Vout), sys0, ncplx, nrun, reach,
+                               launch_gate());
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((tile_sweep_kernel<T, FWD, S, NSET, false>), grid, dim3(256), 0, st,
                        static_cast<const cplx<T>*>(LB), static_cast<const cplx<T>*>(LI), Mx, bp, nsys, nrhs,
                        static_cast<const T*>(Vin), static_cast<T*>(Vout), sys0, ncplx, nrun, reach, launch_gate());
     return hipGetLastError();
