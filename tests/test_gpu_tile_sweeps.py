@@ -36,10 +36,14 @@ pytestmark = pytest.mark.gpu
 
 UNIT_ROUNDOFF = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
 
-# (cells in x, cells in y, right-hand sides): half-bandwidth = cells in x
-TILE_CASES = [(5, 3, 1), (17, 4, 5), (9, 9, 16), (40, 3, 17), (70, 4, 5), (120, 3, 16), (180, 2, 1), (250, 3, 16)]
-TILE_IDS = ["b5_one_block", "b17_three_blocks", "sq9_rhs16", "b40_rhs17", "b70_rhs5", "b120_rhs16", "b180_rhs1",
-            "b250_rhs16"]
+# (cells in x, cells in y, right-hand sides): half-bandwidth = cells in x.
+# M_x = 2 (3 x 2 cells) takes the FP32 kernel variant that reads the
+# entering tile by scalar loads (the 16-byte loads need four rows); the
+# ragged cases (M_x mod 4 = 2, 3) its clamped and shifted 16-byte loads
+TILE_CASES = [(3, 2, 3), (5, 3, 1), (17, 4, 5), (9, 9, 16), (40, 3, 17), (70, 4, 5), (120, 3, 16), (180, 2, 1),
+              (250, 3, 16)]
+TILE_IDS = ["mx2_scalar_tile", "b5_one_block", "b17_three_blocks", "sq9_rhs16", "b40_rhs17", "b70_rhs5", "b120_rhs16",
+            "b180_rhs1", "b250_rhs16"]
 
 
 def _block_cond(S):
